@@ -1,0 +1,358 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle.
+
+Each test checks the oracle (oracle/fno_oracle.c) against something the paper
+or the mathematics fixes: brute-force 4-D sums, a library FFT used as a
+special case, closed-form spectra (impulse, single mode), Parseval/Bessel,
+linearity, adjoint dot-product identities, the identity round trip, exact
+zeroing of truncated modes, the GELU closed form, central finite differences,
+and an independent torch float64 autograd gradient.
+
+P-numbers follow the pin table of the design notes.  The paper (arXiv
+2211.12709) prints no worked numerical example, so no golden values from it
+exist; every pin here is mathematical.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2211_12709_amd import inputs
+
+pytestmark = pytest.mark.filterwarnings("ignore::DeprecationWarning")
+
+TINY = [
+    # (B, Ci, Co, grid, modes)
+    (1, 2, 3, (4, 4, 4, 4), (1, 1, 1, 2)),
+    (2, 3, 2, (6, 5, 4, 6), (2, 2, 1, 3)),
+    (2, 2, 3, (5, 3, 7, 5), (2, 1, 3, 3)),
+    (1, 1, 2, (4, 6, 4, 8), (2, 3, 2, 5)),   # full retention in x, y, z and t (Nyquist kept)
+]
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def rdot(a, b):
+    """Real inner product, complex arrays seen as (re, im) pairs."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.sum(a.real * b.real) + np.sum(a.imag * b.imag))
+
+
+def kset(N, m):
+    return list(range(m)) + list(range(N - m, N))
+
+
+def gather_K(F, d):
+    """Pick the retained modes out of a numpy rfftn spectrum (reading S1)."""
+    (nx, ny, nz, nt), (mx, my, mz, mt) = d.grid, d.modes
+    F = F[:, :, kset(nx, mx)]
+    F = F[:, :, :, kset(ny, my)]
+    F = F[:, :, :, :, kset(nz, mz)]
+    return F[..., :mt]
+
+
+def scatter_K(Fk, d):
+    (nx, ny, nz, nt), (mx, my, mz, mt) = d.grid, d.modes
+    full = np.zeros(Fk.shape[:2] + (nx, ny, nz, nt // 2 + 1), dtype=np.complex128)
+    ix, iy, iz = kset(nx, mx), kset(ny, my), kset(nz, mz)
+    full[np.ix_(range(Fk.shape[0]), range(Fk.shape[1]), ix, iy, iz, range(mt))] = Fk
+    return full
+
+
+def rand_c(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def make(o, spec):
+    B, Ci, Co, grid, modes = spec
+    return o.Dims(B, Ci, Co, grid, modes)
+
+
+# ---------------------------------------------------------------- P1
+@pytest.mark.parametrize("spec", TINY)
+def test_p1_separable_equals_bruteforce(oracle, spec):
+    d = make(oracle, spec)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((d.B, d.Ci, *d.grid))
+    assert rel(oracle.dft_fwd(d, x), oracle.dft_fwd(d, x, direct=True)) < 1e-12
+    F = rand_c(rng, (d.B, d.Co, *d.kshape))
+    wt = oracle.inverse_weights(d)
+    pts = np.arange(d.ncell)
+    direct = oracle.synth_points(d, F, pts, wt).reshape(d.B, d.Co, *d.grid)
+    assert rel(oracle.synth(d, F, wt), direct) < 1e-12
+
+
+# ---------------------------------------------------------------- P2
+@pytest.mark.parametrize("spec", TINY)
+def test_p2_numpy_fft_special_case(oracle, spec):
+    d = make(oracle, spec)
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((d.B, d.Ci, *d.grid))
+    ref = gather_K(np.fft.rfftn(x, axes=(2, 3, 4, 5)), d)
+    assert rel(oracle.dft_fwd(d, x), ref) < 1e-13
+    Y = rand_c(rng, (d.B, d.Co, *d.kshape))
+    S_ref = np.fft.irfftn(scatter_K(Y, d), s=d.grid, axes=(2, 3, 4, 5))
+    assert rel(oracle.synth(d, Y, oracle.inverse_weights(d)), S_ref) < 1e-13
+
+
+def test_p2_numpy_spectral_layer(oracle):
+    d = oracle.Dims(2, 3, 4, (8, 6, 8, 6), (2, 2, 3, 3))
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((d.B, d.Ci, *d.grid))
+    w = rand_c(rng, (d.Ci, d.Co, *d.kshape))
+    Xk = gather_K(np.fft.rfftn(x, axes=(2, 3, 4, 5)), d)
+    Yk = np.einsum("bikxyz,iokxyz->bokxyz", Xk, w)
+    ref = np.fft.irfftn(scatter_K(Yk, d), s=d.grid, axes=(2, 3, 4, 5))
+    y, xh, yh = oracle.spectral_fwd(d, x, w, return_spectra=True)
+    assert rel(xh, Xk) < 1e-13
+    assert rel(yh, Yk) < 1e-13
+    assert rel(y, ref) < 1e-13
+
+
+# ---------------------------------------------------------------- P3
+def test_p3_impulse(oracle):
+    d = oracle.Dims(1, 1, 1, (6, 5, 8, 7), (2, 2, 3, 4))
+    n0 = (4, 1, 6, 5)
+    x = np.zeros((1, 1, *d.grid))
+    x[(0, 0) + n0] = 1.0
+    X = oracle.dft_fwd(d, x)[0, 0]
+    assert np.max(np.abs(np.abs(X) - 1.0)) < 1e-14
+    # phase of every retained mode: exp(-i 2 pi sum k n0 / N)
+    for j in [(0, 0, 0, 0), (1, 3, 2, 3), (3, 0, 5, 1), (2, 2, 4, 2)]:
+        k = [kset(d.grid[a], d.modes[a])[j[a]] for a in range(3)] + [j[3]]
+        th = sum(2 * math.pi * ((k[a] * n0[a]) % d.grid[a]) / d.grid[a] for a in range(4))
+        assert abs(X[j] - complex(math.cos(th), -math.sin(th))) < 1e-14
+
+
+# ---------------------------------------------------------------- P4
+@pytest.mark.parametrize("k0,phi", [((1, 2, 0, 1), 0.3), ((3, 0, 4, 2), -1.1)])
+def test_p4_single_mode(oracle, k0, phi):
+    d = oracle.Dims(1, 1, 1, (8, 6, 10, 8), (2, 2, 3, 3))
+    (nx, ny, nz, nt) = d.grid
+    freqs = [kset(d.grid[a], d.modes[a])[k0[a]] for a in range(3)] + [k0[3]]
+    n = np.meshgrid(*[np.arange(g) for g in d.grid], indexing="ij")
+    th = sum(2 * np.pi * freqs[a] * n[a] / d.grid[a] for a in range(4))
+    x = np.cos(th + phi)[None, None]
+    X = oracle.dft_fwd(d, x)[0, 0]
+    expect = np.zeros(d.kshape, dtype=np.complex128)
+    expect[k0] = d.ncell / 2 * np.exp(1j * phi)
+    assert np.max(np.abs(X - expect)) < 1e-12 * d.ncell
+
+
+# ---------------------------------------------------------------- P5
+@pytest.mark.parametrize("nt", [8, 7])
+def test_p5_parseval_bessel(oracle, nt):
+    full = oracle.Dims(2, 2, 2, (4, 6, 4, nt), (2, 3, 2, nt // 2 + 1))
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((2, 2, *full.grid))
+    X = oracle.dft_fwd(full, x)
+    c = np.array([oracle.ct(k, nt) for k in range(full.modes[3])])
+    energy = np.sum(c * np.abs(X) ** 2, axis=(2, 3, 4, 5)) / full.ncell
+    assert np.max(np.abs(energy - np.sum(x ** 2, axis=(2, 3, 4, 5)))) < 1e-12 * np.sum(x ** 2)
+    trunc = oracle.Dims(2, 2, 2, full.grid, (1, 2, 1, 2))
+    Xt = oracle.dft_fwd(trunc, x)
+    ct_ = c[: trunc.modes[3]]
+    e_t = np.sum(ct_ * np.abs(Xt) ** 2, axis=(2, 3, 4, 5)) / full.ncell
+    assert np.all(e_t <= energy + 1e-12)
+    assert np.all(e_t < 0.9 * energy)   # a truncation really drops energy here
+
+
+# ---------------------------------------------------------------- P6
+def test_p6_linearity(oracle):
+    d = oracle.Dims(2, 2, 3, (6, 5, 4, 6), (2, 2, 1, 3))
+    rng = np.random.default_rng(6)
+    u = rng.standard_normal((2, 2, *d.grid))
+    v = rng.standard_normal((2, 2, *d.grid))
+    a, b = 0.7, -2.3
+    lhs = oracle.dft_fwd(d, a * u + b * v)
+    rhs = a * oracle.dft_fwd(d, u) + b * oracle.dft_fwd(d, v)
+    assert rel(lhs, rhs) < 1e-13
+    w = rand_c(rng, (d.Ci, d.Co, *d.kshape))
+    lhs = oracle.spectral_fwd(d, a * u + b * v, w)
+    rhs = a * oracle.spectral_fwd(d, u, w) + b * oracle.spectral_fwd(d, v, w)
+    assert rel(lhs, rhs) < 1e-13
+
+
+# ---------------------------------------------------------------- P7
+@pytest.mark.parametrize("spec", TINY)
+def test_p7_adjoint_dot_products(oracle, spec):
+    d = make(oracle, spec)
+    rng = np.random.default_rng(7)
+    u = rng.standard_normal((d.B, d.Ci, *d.grid))
+    V = rand_c(rng, (d.B, d.Ci, *d.kshape))
+    # forward DFT vs synthesis with unit weights
+    assert abs(rdot(oracle.dft_fwd(d, u), V) - rdot(u, oracle.synth(d, V))) < 1e-11 * np.abs(V).sum()
+    # real inverse (weights c/N) vs forward DFT weighted by c/N
+    wt = oracle.inverse_weights(d)
+    g = rng.standard_normal((d.B, d.Ci, *d.grid))
+    assert abs(rdot(oracle.synth(d, V, wt), g) - rdot(V, oracle.dft_fwd(d, g, wt))) < 1e-12 * np.abs(g).sum()
+    # mode mix in X^ and in W
+    xh = rand_c(rng, (d.B, d.Ci, *d.kshape))
+    w = rand_c(rng, (d.Ci, d.Co, *d.kshape))
+    gy = rand_c(rng, (d.B, d.Co, *d.kshape))
+    gxh, gw = oracle.mix_bwd(d, xh, w, gy)
+    ref = rdot(oracle.mix(d, xh, w), gy)
+    assert abs(ref - rdot(xh, gxh)) < 1e-11 * abs(ref) + 1e-11
+    assert abs(ref - rdot(w, gw)) < 1e-11 * abs(ref) + 1e-11
+    # whole spectral layer in x and in w
+    v = rng.standard_normal((d.B, d.Co, *d.grid))
+    gx, gw = oracle.spectral_bwd(d, u, w, v)
+    ref = rdot(oracle.spectral_fwd(d, u, w), v)
+    assert abs(ref - rdot(u, gx)) < 1e-11 * abs(ref) + 1e-12
+    assert abs(ref - rdot(w, gw)) < 1e-11 * abs(ref) + 1e-12
+
+
+# ---------------------------------------------------------------- P8
+@pytest.mark.parametrize("grid", [(4, 6, 4, 8), (6, 4, 2, 7)])
+def test_p8_identity_round_trip(oracle, grid):
+    d = oracle.Dims(2, 3, 3, grid, (grid[0] // 2, grid[1] // 2, grid[2] // 2, grid[3] // 2 + 1))
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((2, 3, *grid))
+    w = np.zeros((3, 3, *d.kshape), dtype=np.complex128)
+    for i in range(3):
+        w[i, i] = 1.0
+    assert rel(oracle.spectral_fwd(d, x, w), x) < 1e-13
+
+
+# ---------------------------------------------------------------- P9
+@pytest.mark.parametrize("spec", [(1, 2, 2, (8, 6, 8, 8), (2, 2, 3, 3)),
+                                  (1, 2, 2, (7, 6, 5, 8), (2, 1, 2, 5))])
+def test_p9_truncation_zeroing(oracle, spec):
+    d = make(oracle, spec)
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal((d.B, d.Ci, *d.grid))
+    w = rand_c(rng, (d.Ci, d.Co, *d.kshape))
+    S = oracle.spectral_fwd(d, x, w)
+    F = np.fft.rfftn(S, axes=(2, 3, 4, 5))
+    (nx, ny, nz, nt), (mx, my, mz, mt) = d.grid, d.modes
+    keep = np.zeros((nx, ny, nz, nt // 2 + 1), dtype=bool)
+    keep[np.ix_(kset(nx, mx), kset(ny, my), kset(nz, mz), range(mt))] = True
+    # k_t = 0 (and the kept Nyquist bin) are Hermitian planes: their mirror
+    # -k carries the conjugate of what the real part keeps (reading S4)
+    planes = [0] + ([nt // 2] if nt % 2 == 0 and mt == nt // 2 + 1 else [])
+    mir = keep.copy()
+    for kt in planes:
+        for ix in range(nx):
+            for iy in range(ny):
+                for iz in range(nz):
+                    if keep[ix, iy, iz, kt]:
+                        mir[(-ix) % nx, (-iy) % ny, (-iz) % nz, kt] = True
+    outside = np.abs(F[:, :, ~mir])
+    assert outside.max() < 1e-13 * np.abs(F).max()
+    # and the spectrum is not zero on K itself
+    assert np.abs(F[:, :, keep]).max() > 1e-3 * np.abs(F).max()
+
+
+# ---------------------------------------------------------------- P10
+def test_p10_gelu(oracle):
+    for u in [-6.0, -2.5, -1.0, -0.3, 0.0, 0.2, 1.0, 3.7, 9.0]:
+        ref = 0.5 * u * (1 + math.erf(u / math.sqrt(2)))
+        assert abs(oracle.gelu(u) - ref) <= 1e-15 * max(1, abs(u))
+        h = 1e-5
+        fd = (oracle.gelu(u + h) - oracle.gelu(u - h)) / (2 * h)
+        assert abs(oracle.gelu_grad(u) - fd) < 1e-9
+    assert oracle.gelu(0.0) == 0.0
+    assert oracle.gelu_grad(0.0) == 0.5
+    assert abs(oracle.gelu(10.0) - 10.0) < 1e-15
+
+
+# ---------------------------------------------------------------- P11
+def _block_loss(oracle, d, x, w, wpw, bpw, gy):
+    return float(np.sum(oracle.block_fwd(d, x, w, wpw, bpw) * gy))
+
+
+@pytest.mark.parametrize("spec", [(2, 3, 2, (6, 5, 4, 6), (2, 2, 1, 3)),
+                                  (1, 4, 4, (8, 8, 6, 8), (2, 3, 2, 4))])
+def test_p11_finite_differences(oracle, spec):
+    d = make(oracle, spec)
+    rng = np.random.default_rng(inputs.SEED_FD)
+    x = rng.standard_normal((d.B, d.Ci, *d.grid))
+    w = rand_c(rng, (d.Ci, d.Co, *d.kshape)) * 0.3
+    wpw = rng.standard_normal((d.Co, d.Ci)) * 0.4
+    bpw = rng.standard_normal(d.Co) * 0.2
+    gy = rng.standard_normal((d.B, d.Co, *d.grid))
+    gx, gw, gwpw, gb = oracle.block_bwd(d, x, w, wpw, bpw, gy)
+    eps = 1e-3
+    L = lambda **kw: _block_loss(oracle, d, kw.get("x", x), kw.get("w", w), kw.get("wpw", wpw),
+                                 kw.get("bpw", bpw), gy)
+    checks = []
+    for _ in range(8):   # 8 complex weights = 16 real directions
+        idx = tuple(int(rng.integers(0, s)) for s in w.shape)
+        for part, unit in ((0, 1.0), (1, 1j)):
+            wp, wm = w.copy(), w.copy()
+            wp[idx] += eps * unit
+            wm[idx] -= eps * unit
+            fd = (L(w=wp) - L(w=wm)) / (2 * eps)
+            an = gw[idx].real if part == 0 else gw[idx].imag
+            checks.append((fd, an))
+    for _ in range(6):
+        idx = tuple(int(rng.integers(0, s)) for s in wpw.shape)
+        p, m = wpw.copy(), wpw.copy()
+        p[idx] += eps
+        m[idx] -= eps
+        checks.append(((L(wpw=p) - L(wpw=m)) / (2 * eps), gwpw[idx]))
+    for o in range(min(d.Co, 2)):
+        p, m = bpw.copy(), bpw.copy()
+        p[o] += eps
+        m[o] -= eps
+        checks.append(((L(bpw=p) - L(bpw=m)) / (2 * eps), gb[o]))
+    for _ in range(8):
+        idx = tuple(int(rng.integers(0, s)) for s in x.shape)
+        p, m = x.copy(), x.copy()
+        p[idx] += eps
+        m[idx] -= eps
+        checks.append(((L(x=p) - L(x=m)) / (2 * eps), gx[idx]))
+    assert len(checks) >= 32
+    scale = max(abs(a) for _, a in checks)
+    for fd, an in checks:
+        assert abs(fd - an) <= 1e-6 * scale + 1e-6 * abs(an), (fd, an)
+
+
+# ---------------------------------------------------------------- P12
+@pytest.mark.parametrize("spec", [(2, 3, 2, (6, 5, 4, 6), (2, 2, 1, 3)),
+                                  (1, 2, 3, (8, 6, 8, 8), (3, 2, 2, 5))])
+def test_p12_torch_autograd_gradient(oracle, spec):
+    torch = pytest.importorskip("torch")
+    d = make(oracle, spec)
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal((d.B, d.Ci, *d.grid))
+    w = rand_c(rng, (d.Ci, d.Co, *d.kshape)) * 0.3
+    wpw = rng.standard_normal((d.Co, d.Ci)) * 0.4
+    bpw = rng.standard_normal(d.Co) * 0.2
+    gy = rng.standard_normal((d.B, d.Co, *d.grid))
+
+    tx = torch.tensor(x, requires_grad=True)
+    tw = torch.tensor(w, requires_grad=True)
+    twp = torch.tensor(wpw, requires_grad=True)
+    tb = torch.tensor(bpw, requires_grad=True)
+    (nx, ny, nz, nt), (mx, my, mz, mt) = d.grid, d.modes
+    ix, iy, iz = (torch.tensor(kset(n, m)) for n, m in ((nx, mx), (ny, my), (nz, mz)))
+    X = torch.fft.rfftn(tx, dim=(2, 3, 4, 5))
+    Xk = X.index_select(2, ix).index_select(3, iy).index_select(4, iz)[..., :mt]
+    Yk = torch.einsum("bikxyz,iokxyz->bokxyz", Xk, tw)
+    full = torch.zeros((d.B, d.Co, nx, ny, nz, nt // 2 + 1), dtype=torch.complex128)
+    full[:, :, ix[:, None, None], iy[None, :, None], iz[None, None, :], :mt] = Yk
+    S = torch.fft.irfftn(full, s=d.grid, dim=(2, 3, 4, 5))
+    Z = S + torch.einsum("oi,bixyzt->boxyzt", twp, tx) + tb[None, :, None, None, None, None]
+    y = torch.nn.functional.gelu(Z)
+    (y * torch.tensor(gy)).sum().backward()
+
+    y_o = oracle.block_fwd(d, x, w, wpw, bpw)
+    assert rel(y_o, y.detach().numpy()) < 1e-13
+    gx, gw, gwpw, gb = oracle.block_bwd(d, x, w, wpw, bpw, gy)
+    assert rel(gx, tx.grad.numpy()) < 1e-12
+    assert rel(gw, tw.grad.numpy()) < 1e-12
+    assert rel(gwpw, twp.grad.numpy()) < 1e-12
+    assert rel(gb, tb.grad.numpy()) < 1e-12
+
+
+# ---------------------------------------------------------------- shapes
+def test_dims_validation(oracle):
+    assert oracle.check_dims(oracle.Dims(1, 1, 1, (4, 4, 4, 4), (2, 2, 2, 3)))
+    assert not oracle.check_dims(oracle.Dims(1, 1, 1, (4, 4, 4, 4), (3, 2, 2, 3)))   # 2m > N
+    assert not oracle.check_dims(oracle.Dims(1, 1, 1, (4, 4, 4, 4), (2, 2, 2, 4)))   # mt > Nt/2+1
+    assert not oracle.check_dims(oracle.Dims(0, 1, 1, (4, 4, 4, 4), (1, 1, 1, 1)))
