@@ -1,0 +1,138 @@
+/*
+ * fno_mi355x.h -- C-ABI of the MI355X (gfx950) 4-D spectral-convolution FNO
+ * block library, libfno_mi355x.so.
+ *
+ * The operation is the FNO block of arXiv 2211.12709 ("SciAI4Industry"),
+ * Sec. IV-C, Alg. 1 (encoder, FNO blocks, decoder) and Alg. 2 (distributed FNO
+ * block): a truncated forward real DFT over x, y, z, t, a per-retained-mode
+ * complex channel mix (einsum over c_in, elementwise over k), a zero-padded
+ * inverse DFT, and, for the block, the pointwise 1x1 channel linear plus bias
+ * beside it, inside the activation sigma (GELU, erf form).
+ *
+ * Definitions (n = (x, y, z, t) grid point, k = (kx, ky, kz, kt) retained mode,
+ * theta(k, n) = 2*pi*(kx x/Nx + ky y/Ny + kz z/Nz + kt t/Nt), N = Nx Ny Nz Nt):
+ *   retained set K: on x, y, z the m lowest non-negative and the m lowest
+ *     negative frequencies (compact index j -> frequency j for j < m and
+ *     N_d - 2m + j for j >= m); on t the m_t lowest non-negative bins.
+ *   X^[b,i,k]  = sum_n x[b,i,n] exp(-i theta(k,n))                 (Alg. 2, line 1)
+ *   Y^[b,o,k]  = sum_i X^[b,i,k] W[i,o,k]                          (Alg. 2, line 2)
+ *   S[b,o,n]   = (1/N) sum_k c(kt) Re(Y^[b,o,k] exp(+i theta(k,n))) (Alg. 2, line 3)
+ *     with c(0) = 1, c(Nt/2) = 1 for even Nt, c = 2 otherwise (real inverse of
+ *     the zero-padded spectrum).
+ *   block:  y = GELU(S + W_pw x + b_pw),  GELU(u) = u/2 (1 + erf(u/sqrt 2)) (Alg. 1)
+ * Gradients use the convention g = dL/dRe + i dL/dIm for complex tensors.
+ *
+ * Layouts (all dense, C order, device memory, 16-byte aligned):
+ *   x, gx          [B][C_in ][Nx][Ny][Nz][Nt]   activation dtype (desc.dtype)
+ *   y, gy          [B][C_out][Nx][Ny][Nz][Nt]   activation dtype
+ *   w, gw          [C_in][C_out][2mx][2my][2mz][mt] complex float (re, im interleaved)
+ *   w_pw, gw_pw    [C_out][C_in] float
+ *   b_pw, gb_pw    [C_out] float
+ *   activation dtype: FNO_F32 = float, FNO_BF16 = bfloat16 (round-to-nearest-even)
+ *
+ * Ownership: the caller allocates and owns every tensor, the workspace and the
+ * cache; the library owns only the plan and its device basis tables.  All
+ * work is enqueued on `stream` (a hipStream_t, NULL = default stream) without
+ * host synchronisation.  No C++ exception crosses this interface.
+ *
+ * Errors: every entry point returns an fno_status_t.  Argument, alignment and
+ * workspace checks happen on the host before anything is launched; a HIP
+ * launch error is returned as FNO_ERR_HIP.  Calls on distinct workspaces and
+ * caches may run concurrently on different streams with one plan.
+ */
+#ifndef FNO_MI355X_H
+#define FNO_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FNO_OK = 0,
+    FNO_ERR_INVALID_ARG = 1, /* null pointer, non-positive size, mode count out of range  */
+    FNO_ERR_UNSUPPORTED = 2, /* valid but not implemented (dtype, sizes beyond limits)    */
+    FNO_ERR_ALIGNMENT = 3,   /* a tensor pointer not 16-byte aligned                       */
+    FNO_ERR_WORKSPACE = 4,   /* workspace or cache smaller than fno_workspace_bytes / fno_cache_bytes */
+    FNO_ERR_HIP = 5,         /* HIP runtime or launch error                                */
+    FNO_ERR_OOM = 6          /* device allocation failed (plan creation only)              */
+} fno_status_t;
+
+enum { FNO_F32 = 0, FNO_BF16 = 1 };
+
+enum {
+    FNO_OP_SPECTRAL_FWD = 0,
+    FNO_OP_SPECTRAL_BWD = 1,
+    FNO_OP_BLOCK_FWD = 2,
+    FNO_OP_BLOCK_BWD = 3
+};
+
+/* Problem descriptor: the arguments of the layer in Sec. IV-C -- batch,
+ * channels, grid (x, y, z, t), retained modes per axis.
+ * Requires B, C_in, C_out, grid[d], modes[d] >= 1; 2*modes[d] <= grid[d] for
+ * d = x, y, z; modes[3] <= grid[3]/2 + 1.  flags must be 0 (reserved). */
+typedef struct {
+    int32_t B, C_in, C_out;
+    int32_t grid[4];  /* Nx, Ny, Nz, Nt */
+    int32_t modes[4]; /* mx, my, mz, mt */
+    int32_t dtype;    /* FNO_F32 or FNO_BF16: storage/compute type of activations */
+    uint32_t flags;
+} fno_desc_t;
+
+typedef struct fno_plan fno_plan_t;
+
+/* Host-only check of a descriptor (no HIP call).  FNO_OK or FNO_ERR_INVALID_ARG
+ * (or FNO_ERR_UNSUPPORTED for a dtype/flag this build does not provide). */
+int fno_desc_validate(const fno_desc_t *desc);
+
+/* Create a plan on the current HIP device: validates `desc`, allocates the
+ * basis tables and generates them in FP64 (exact integer phase reduction),
+ * rounded once to the kernel types.  Synchronises the device before return.
+ * *out is NULL on failure. */
+int fno_plan_create(fno_plan_t **out, const fno_desc_t *desc);
+int fno_plan_destroy(fno_plan_t *plan);
+
+/* Workspace bytes one call of operation `op` (FNO_OP_*) needs. */
+int fno_workspace_bytes(const fno_plan_t *plan, int op, size_t *out);
+/* Bytes of the forward cache (retained spectrum X^ and the x-inverse of Y^)
+ * written by fno_spectral_fwd / fno_block_fwd and read by the backward calls. */
+int fno_cache_bytes(const fno_plan_t *plan, size_t *out);
+
+/* Spectral convolution layer (Alg. 2): y = S(x; w).  cache (nullable)
+ * receives what the backward needs. */
+int fno_spectral_fwd(const fno_plan_t *plan, const void *x, const void *w, void *y,
+                     void *cache, void *ws, size_t ws_bytes, void *stream);
+
+/* Backward of the spectral layer: gx = adjoint of x -> y applied to gy
+ * (nullable: skipped); gw = sum_b conj(X^) * (c(kt)/N) DFT(gy)  (nullable:
+ * skipped).  gw needs the spectrum of x: from `cache` if non-NULL (as written
+ * by fno_spectral_fwd with the same x), else recomputed from `x`.
+ * accumulate != 0 adds into gx / gw instead of overwriting. */
+int fno_spectral_bwd(const fno_plan_t *plan, const void *x, const void *cache, const void *w,
+                     const void *gy, void *gx, void *gw, int accumulate,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/* FNO block (Alg. 1, block line): y = GELU(S(x; w) + w_pw x + b_pw).
+ * b_pw may be NULL (no bias).  cache (nullable) receives what fno_block_bwd
+ * needs to recompute the pre-activation (the full-size pre-activation itself
+ * is never stored). */
+int fno_block_fwd(const fno_plan_t *plan, const void *x, const void *w, const void *w_pw,
+                  const void *b_pw, void *y, void *cache, void *ws, size_t ws_bytes, void *stream);
+
+/* Backward of the FNO block with recomputation of the pre-activation from x
+ * and `cache` (required, written by fno_block_fwd with the same x, w).
+ * Outputs gx (required), gw, gw_pw, gb_pw (each nullable).  accumulate != 0
+ * adds into every output instead of overwriting. */
+int fno_block_bwd(const fno_plan_t *plan, const void *x, const void *cache, const void *w,
+                  const void *w_pw, const void *b_pw, const void *gy, void *gx, void *gw,
+                  void *gw_pw, void *gb_pw, int accumulate, void *ws, size_t ws_bytes, void *stream);
+
+/* Static description of a status code. */
+const char *fno_status_str(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FNO_MI355X_H */

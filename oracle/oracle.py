@@ -97,6 +97,10 @@ class Dims:
     def ncell(self):
         return int(np.prod(self.grid))
 
+    @property
+    def nmode(self):
+        return int(np.prod(self.kshape))
+
     def vec(self):
         v = [self.B, self.Ci, self.Co, *self.grid, *self.modes]
         return (ctypes.c_int * 11)(*v)

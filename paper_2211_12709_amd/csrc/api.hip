@@ -1,0 +1,366 @@
+// api.hip -- host side of the C-ABI declared in include/fno_mi355x.h:
+// descriptor validation, plans (device basis tables), workspace and cache
+// sizing, argument checks, and the launch sequences of the four entry points.
+//
+// Launch sequences (Alg. 2 of arXiv 2211.12709, truncation applied as each
+// axis is transformed, t first, x last; the inverse runs in reverse order):
+//   forward spectrum:  activations -t,z-> T1 -y-> T2 -x-> X^
+//   mix:               Y^ = X^ W per retained mode
+//   inverse:           Y^ -x-> U2 -y-> U1 -z,t + epilogue-> output
+#include <algorithm>
+#include <new>
+
+#include "fno_internal.h"
+
+namespace fno {
+
+hipError_t generate_tables(const Dims &d, Tables &t, hipStream_t st);
+void launch_axis(const float2 *in, float2 *out, const float2 *tab, long long outer, int Nin, int Nout,
+                 long long inner, int N, int inverse, hipStream_t st);
+void launch_mix_fwd(const float2 *xh, const float2 *w, float2 *yh, int B, int Ci, int Co, long long M, hipStream_t st);
+void launch_mix_bwd(const float2 *xh, const float2 *w, const float2 *gyh, float2 *gxh, float2 *gw, int B, int Ci,
+                    int Co, long long M, int accumulate, hipStream_t st);
+int pw_wgrad_chunks(long long total);
+template <typename T>
+void launch_pw_wgrad(const float *gz, const T *x, float *part, float *gwpw, float *gb, int B, int Ci, int Co,
+                     long long ncell, int accumulate, hipStream_t st);
+template <typename T>
+void launch_fwd_tz(const T *in, float2 *out, long long planes, const Dims &d, const Tables &tab, const float *wt,
+                   hipStream_t st);
+template <typename T>
+void launch_inv_zt(int epi, const float2 *u, T *out, int C, const Dims &d, const Tables &tab, const float *wt,
+                   const T *x, const float *wpw, const float *bpw, const float *gz, int Cx, int accumulate,
+                   hipStream_t st);
+template <typename T>
+void launch_bwd_gz(const float2 *u, const T *x, const T *gy, float *gz, const Dims &d, const Tables &tab,
+                   const float *wpw, const float *bpw, hipStream_t st);
+size_t fwd_tz_lds(const Dims &d);
+size_t inv_zt_lds(const Dims &d);
+
+enum { EPI_PLAIN = 0, EPI_BLOCK = 1, EPI_ADJ = 2 };
+
+static const int kMaxChannels = 64;
+static const size_t kMaxLds = 65536;
+
+static size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+static int dims_from_desc(const fno_desc_t *s, Dims *d)
+{
+    if (!s) return FNO_ERR_INVALID_ARG;
+    if (s->B < 1 || s->C_in < 1 || s->C_out < 1) return FNO_ERR_INVALID_ARG;
+    for (int a = 0; a < 4; a++)
+        if (s->grid[a] < 1 || s->modes[a] < 1) return FNO_ERR_INVALID_ARG;
+    for (int a = 0; a < 3; a++)
+        if (2LL * s->modes[a] > s->grid[a]) return FNO_ERR_INVALID_ARG;
+    if (s->modes[3] > s->grid[3] / 2 + 1) return FNO_ERR_INVALID_ARG;
+    if (s->dtype != FNO_F32 && s->dtype != FNO_BF16) return FNO_ERR_UNSUPPORTED;
+    if (s->flags != 0) return FNO_ERR_UNSUPPORTED;
+    d->B = s->B;
+    d->Ci = s->C_in;
+    d->Co = s->C_out;
+    for (int a = 0; a < 4; a++) {
+        d->N[a] = s->grid[a];
+        d->m[a] = s->modes[a];
+        d->K[a] = a < 3 ? 2 * s->modes[a] : s->modes[a];
+    }
+    d->ncell = (long long)d->N[0] * d->N[1] * d->N[2] * d->N[3];
+    d->nmode = (long long)d->K[0] * d->K[1] * d->K[2] * d->K[3];
+    d->plane = (long long)d->N[2] * d->N[3];
+    d->kplane = (long long)d->K[2] * d->K[3];
+    d->P = (long long)d->K[1] * d->K[2] * d->K[3];
+    // limits of this implementation
+    if (d->Ci > kMaxChannels || d->Co > kMaxChannels) return FNO_ERR_UNSUPPORTED;
+    if (fwd_tz_lds(*d) > kMaxLds || inv_zt_lds(*d) > kMaxLds) return FNO_ERR_UNSUPPORTED;
+    if ((long long)d->B * std::max(d->Ci, d->Co) * d->N[0] * d->N[1] > 0x7fffffffLL) return FNO_ERR_UNSUPPORTED;
+    return FNO_OK;
+}
+
+// Workspace layout (bytes, each part 256-byte aligned).
+struct WsPlan {
+    size_t t1, t2, sp, sp2, sp3, gz, part, total;
+};
+
+static WsPlan ws_plan(const Dims &d, int op)
+{
+    const long long C = std::max(d.Ci, d.Co);
+    WsPlan w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align_up(bytes); return o; };
+    w.t1 = take(sizeof(float2) * (size_t)(d.B * C * d.N[0] * d.N[1] * d.kplane));
+    w.t2 = take(sizeof(float2) * (size_t)(d.B * C * d.N[0] * d.P));
+    w.sp = take(sizeof(float2) * (size_t)(d.B * C * d.nmode));
+    w.sp2 = take(sizeof(float2) * (size_t)(d.B * C * d.nmode));
+    w.sp3 = take(sizeof(float2) * (size_t)(d.B * C * d.nmode));
+    if (op == FNO_OP_BLOCK_BWD) {
+        w.gz = take(sizeof(float) * (size_t)(d.B * d.Co * d.ncell));
+        w.part = take(sizeof(float) * (size_t)pw_wgrad_chunks(d.B * d.ncell) * d.Co * (d.Ci + 1));
+    }
+    w.total = off;
+    return w;
+}
+
+static size_t cache_xh_bytes(const Dims &d) { return align_up(sizeof(float2) * (size_t)(d.B * d.Ci * d.nmode)); }
+static size_t cache_bytes(const Dims &d)
+{
+    return cache_xh_bytes(d) + align_up(sizeof(float2) * (size_t)(d.B * d.Co * d.N[0] * d.P));
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+static int check_plan(const fno_plan_t *plan)
+{
+    if (!plan) return FNO_ERR_INVALID_ARG;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return FNO_ERR_HIP;
+    if (dev != plan->device) return FNO_ERR_INVALID_ARG;
+    return FNO_OK;
+}
+
+static int finish()
+{
+    return hipGetLastError() == hipSuccess ? FNO_OK : FNO_ERR_HIP;
+}
+
+// X^ of activations `in` (C channels) into xh, using t1/t2 as scratch.
+template <typename T>
+static void forward_spectrum(const fno_plan_t *p, const T *in, int C, const float *wt, float2 *t1, float2 *t2,
+                             float2 *xh, hipStream_t st)
+{
+    const Dims &d = p->d;
+    launch_fwd_tz<T>(in, t1, (long long)d.B * C * d.N[0] * d.N[1], d, p->tab, wt, st);
+    launch_axis(t1, t2, p->tab.cs[1], (long long)d.B * C * d.N[0], d.N[1], d.K[1], d.kplane, d.N[1], 0, st);
+    launch_axis(t2, xh, p->tab.cs[0], (long long)d.B * C, d.N[0], d.K[0], d.P, d.N[0], 0, st);
+}
+
+// Inverse x then y stage of a retained spectrum (C channels): spec -> u2 -> u1.
+static void inverse_xy(const fno_plan_t *p, const float2 *spec, int C, float2 *u2, float2 *u1, hipStream_t st,
+                       bool skip_x = false)
+{
+    const Dims &d = p->d;
+    if (!skip_x) launch_axis(spec, u2, p->tab.cs[0], (long long)d.B * C, d.K[0], d.N[0], d.P, d.N[0], 1, st);
+    launch_axis(u2, u1, p->tab.cs[1], (long long)d.B * C * d.N[0], d.K[1], d.N[1], d.kplane, d.N[1], 1, st);
+}
+
+template <typename T>
+static int spectral_or_block_fwd(const fno_plan_t *p, const void *x_, const void *w_, const void *wpw, const void *bpw,
+                                 void *y_, void *cache, void *ws, size_t ws_bytes, void *stream, bool block)
+{
+    const Dims &d = p->d;
+    const int op = block ? FNO_OP_BLOCK_FWD : FNO_OP_SPECTRAL_FWD;
+    WsPlan wp = ws_plan(d, op);
+    if (!x_ || !w_ || !y_ || !ws || (block && !wpw)) return FNO_ERR_INVALID_ARG;
+    if (!aligned16(x_) || !aligned16(w_) || !aligned16(y_) || !aligned16(ws) || (cache && !aligned16(cache)) ||
+        (wpw && !aligned16(wpw)) || (bpw && !aligned16(bpw)))
+        return FNO_ERR_ALIGNMENT;
+    if (ws_bytes < wp.total) return FNO_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    char *wb = (char *)ws;
+    float2 *t1 = (float2 *)(wb + wp.t1), *t2 = (float2 *)(wb + wp.t2);
+    float2 *xh = cache ? (float2 *)cache : (float2 *)(wb + wp.sp);
+    float2 *u2 = cache ? (float2 *)((char *)cache + cache_xh_bytes(d)) : t2;
+    float2 *yh = (float2 *)(wb + wp.sp2);
+    const T *x = (const T *)x_;
+    forward_spectrum<T>(p, x, d.Ci, p->tab.wt_one, t1, t2, xh, st);
+    launch_mix_fwd(xh, (const float2 *)w_, yh, d.B, d.Ci, d.Co, d.nmode, st);
+    inverse_xy(p, yh, d.Co, u2, t1, st);
+    launch_inv_zt<T>(block ? EPI_BLOCK : EPI_PLAIN, t1, (T *)y_, d.Co, d, p->tab, p->tab.wt_inv, x,
+                     (const float *)wpw, (const float *)bpw, nullptr, d.Ci, 0, st);
+    return finish();
+}
+
+template <typename T>
+static int spectral_bwd_impl(const fno_plan_t *p, const void *x_, const void *cache, const void *w_, const void *gy_,
+                             void *gx_, void *gw_, int accumulate, void *ws, size_t ws_bytes, void *stream)
+{
+    const Dims &d = p->d;
+    WsPlan wp = ws_plan(d, FNO_OP_SPECTRAL_BWD);
+    if (!w_ || !gy_ || !ws) return FNO_ERR_INVALID_ARG;
+    if (gw_ && !cache && !x_) return FNO_ERR_INVALID_ARG;
+    if (!aligned16(w_) || !aligned16(gy_) || !aligned16(ws) || (x_ && !aligned16(x_)) || (cache && !aligned16(cache)) ||
+        (gx_ && !aligned16(gx_)) || (gw_ && !aligned16(gw_)))
+        return FNO_ERR_ALIGNMENT;
+    if (ws_bytes < wp.total) return FNO_ERR_WORKSPACE;
+    if (!gx_ && !gw_) return FNO_OK;
+    hipStream_t st = (hipStream_t)stream;
+    char *wb = (char *)ws;
+    float2 *t1 = (float2 *)(wb + wp.t1), *t2 = (float2 *)(wb + wp.t2);
+    float2 *sp = (float2 *)(wb + wp.sp), *gyh = (float2 *)(wb + wp.sp2), *gxh = (float2 *)(wb + wp.sp3);
+    const float2 *xh = nullptr;
+    if (gw_) {
+        if (cache) {
+            xh = (const float2 *)cache;
+        } else {
+            forward_spectrum<T>(p, (const T *)x_, d.Ci, p->tab.wt_one, t1, t2, sp, st);
+            xh = sp;
+        }
+    }
+    // adjoint of the real inverse: gY^ = (c(kt)/N) sum_n gy exp(-i theta)
+    forward_spectrum<T>(p, (const T *)gy_, d.Co, p->tab.wt_inv, t1, t2, gyh, st);
+    launch_mix_bwd(xh, (const float2 *)w_, gyh, gx_ ? gxh : nullptr, (float2 *)gw_, d.B, d.Ci, d.Co, d.nmode,
+                   accumulate, st);
+    if (gx_) {
+        inverse_xy(p, gxh, d.Ci, t2, t1, st);
+        launch_inv_zt<T>(EPI_ADJ, t1, (T *)gx_, d.Ci, d, p->tab, p->tab.wt_one, nullptr, nullptr, nullptr, nullptr,
+                         d.Co, accumulate, st);
+    }
+    return finish();
+}
+
+template <typename T>
+static int block_bwd_impl(const fno_plan_t *p, const void *x_, const void *cache, const void *w_, const void *wpw_,
+                          const void *bpw_, const void *gy_, void *gx_, void *gw_, void *gwpw_, void *gb_,
+                          int accumulate, void *ws, size_t ws_bytes, void *stream)
+{
+    const Dims &d = p->d;
+    WsPlan wp = ws_plan(d, FNO_OP_BLOCK_BWD);
+    if (!x_ || !cache || !w_ || !wpw_ || !gy_ || !gx_ || !ws) return FNO_ERR_INVALID_ARG;
+    if (!aligned16(x_) || !aligned16(cache) || !aligned16(w_) || !aligned16(wpw_) || (bpw_ && !aligned16(bpw_)) ||
+        !aligned16(gy_) || !aligned16(gx_) || (gw_ && !aligned16(gw_)) || (gwpw_ && !aligned16(gwpw_)) ||
+        (gb_ && !aligned16(gb_)) || !aligned16(ws))
+        return FNO_ERR_ALIGNMENT;
+    if (ws_bytes < wp.total) return FNO_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    char *wb = (char *)ws;
+    float2 *t1 = (float2 *)(wb + wp.t1), *t2 = (float2 *)(wb + wp.t2);
+    float2 *gyh = (float2 *)(wb + wp.sp2), *gxh = (float2 *)(wb + wp.sp3);
+    float *gz = (float *)(wb + wp.gz), *part = (float *)(wb + wp.part);
+    const float2 *xh = (const float2 *)cache;
+    const float2 *u2 = (const float2 *)((const char *)cache + cache_xh_bytes(d));
+    const T *x = (const T *)x_;
+    const float *wpw = (const float *)wpw_, *bpw = (const float *)bpw_;
+    // recompute the pre-activation from the cached x-inverse of Y^, then gz
+    inverse_xy(p, nullptr, d.Co, const_cast<float2 *>(u2), t1, st, true);
+    launch_bwd_gz<T>(t1, x, (const T *)gy_, gz, d, p->tab, wpw, bpw, st);
+    if (gwpw_ || gb_) launch_pw_wgrad<T>(gz, x, part, (float *)gwpw_, (float *)gb_, d.B, d.Ci, d.Co, d.ncell, accumulate, st);
+    // spectral part: gY^ = (c/N) DFT(gz), then the mix gradients and the adjoint
+    forward_spectrum<float>(p, gz, d.Co, p->tab.wt_inv, t1, t2, gyh, st);
+    launch_mix_bwd(xh, (const float2 *)w_, gyh, gxh, (float2 *)gw_, d.B, d.Ci, d.Co, d.nmode, accumulate, st);
+    inverse_xy(p, gxh, d.Ci, t2, t1, st);
+    launch_inv_zt<T>(EPI_ADJ, t1, (T *)gx_, d.Ci, d, p->tab, p->tab.wt_one, nullptr, wpw, nullptr, gz, d.Co,
+                     accumulate, st);
+    return finish();
+}
+
+}  // namespace fno
+
+using namespace fno;
+
+extern "C" {
+
+int fno_desc_validate(const fno_desc_t *desc)
+{
+    Dims d;
+    return dims_from_desc(desc, &d);
+}
+
+int fno_plan_create(fno_plan_t **out, const fno_desc_t *desc)
+{
+    if (!out) return FNO_ERR_INVALID_ARG;
+    *out = nullptr;
+    Dims d;
+    int rc = dims_from_desc(desc, &d);
+    if (rc != FNO_OK) return rc;
+    fno_plan_t *p = new (std::nothrow) fno_plan_t();
+    if (!p) return FNO_ERR_OOM;
+    p->desc = *desc;
+    p->d = d;
+    if (hipGetDevice(&p->device) != hipSuccess) { delete p; return FNO_ERR_HIP; }
+    size_t off[6], tot = 0;
+    for (int a = 0; a < 4; a++) { off[a] = tot; tot += align_up(sizeof(float2) * (size_t)d.K[a] * d.N[a]); }
+    off[4] = tot; tot += align_up(sizeof(float) * d.K[3]);
+    off[5] = tot; tot += align_up(sizeof(float) * d.K[3]);
+    if (hipMalloc(&p->table_mem, tot) != hipSuccess) { (void)hipGetLastError(); delete p; return FNO_ERR_OOM; }
+    char *base = (char *)p->table_mem;
+    for (int a = 0; a < 4; a++) p->tab.cs[a] = (float2 *)(base + off[a]);
+    p->tab.wt_inv = (float *)(base + off[4]);
+    p->tab.wt_one = (float *)(base + off[5]);
+    if (generate_tables(d, p->tab, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+        (void)hipFree(p->table_mem);
+        delete p;
+        return FNO_ERR_HIP;
+    }
+    *out = p;
+    return FNO_OK;
+}
+
+int fno_plan_destroy(fno_plan_t *plan)
+{
+    if (!plan) return FNO_ERR_INVALID_ARG;
+    int rc = FNO_OK;
+    if (plan->table_mem && hipFree(plan->table_mem) != hipSuccess) rc = FNO_ERR_HIP;
+    delete plan;
+    return rc;
+}
+
+int fno_workspace_bytes(const fno_plan_t *plan, int op, size_t *out)
+{
+    if (!plan || !out || op < FNO_OP_SPECTRAL_FWD || op > FNO_OP_BLOCK_BWD) return FNO_ERR_INVALID_ARG;
+    *out = ws_plan(plan->d, op).total;
+    return FNO_OK;
+}
+
+int fno_cache_bytes(const fno_plan_t *plan, size_t *out)
+{
+    if (!plan || !out) return FNO_ERR_INVALID_ARG;
+    *out = cache_bytes(plan->d);
+    return FNO_OK;
+}
+
+int fno_spectral_fwd(const fno_plan_t *plan, const void *x, const void *w, void *y, void *cache, void *ws,
+                     size_t ws_bytes, void *stream)
+{
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (plan->desc.dtype == FNO_BF16)
+        return spectral_or_block_fwd<__bf16>(plan, x, w, nullptr, nullptr, y, cache, ws, ws_bytes, stream, false);
+    return spectral_or_block_fwd<float>(plan, x, w, nullptr, nullptr, y, cache, ws, ws_bytes, stream, false);
+}
+
+int fno_spectral_bwd(const fno_plan_t *plan, const void *x, const void *cache, const void *w, const void *gy, void *gx,
+                     void *gw, int accumulate, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (plan->desc.dtype == FNO_BF16)
+        return spectral_bwd_impl<__bf16>(plan, x, cache, w, gy, gx, gw, accumulate, ws, ws_bytes, stream);
+    return spectral_bwd_impl<float>(plan, x, cache, w, gy, gx, gw, accumulate, ws, ws_bytes, stream);
+}
+
+int fno_block_fwd(const fno_plan_t *plan, const void *x, const void *w, const void *w_pw, const void *b_pw, void *y,
+                  void *cache, void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (plan->desc.dtype == FNO_BF16)
+        return spectral_or_block_fwd<__bf16>(plan, x, w, w_pw, b_pw, y, cache, ws, ws_bytes, stream, true);
+    return spectral_or_block_fwd<float>(plan, x, w, w_pw, b_pw, y, cache, ws, ws_bytes, stream, true);
+}
+
+int fno_block_bwd(const fno_plan_t *plan, const void *x, const void *cache, const void *w, const void *w_pw,
+                  const void *b_pw, const void *gy, void *gx, void *gw, void *gw_pw, void *gb_pw, int accumulate,
+                  void *ws, size_t ws_bytes, void *stream)
+{
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (plan->desc.dtype == FNO_BF16)
+        return block_bwd_impl<__bf16>(plan, x, cache, w, w_pw, b_pw, gy, gx, gw, gw_pw, gb_pw, accumulate, ws,
+                                      ws_bytes, stream);
+    return block_bwd_impl<float>(plan, x, cache, w, w_pw, b_pw, gy, gx, gw, gw_pw, gb_pw, accumulate, ws, ws_bytes,
+                                 stream);
+}
+
+const char *fno_status_str(int status)
+{
+    switch (status) {
+    case FNO_OK: return "FNO_OK";
+    case FNO_ERR_INVALID_ARG: return "FNO_ERR_INVALID_ARG: null pointer, bad size or mode count out of range";
+    case FNO_ERR_UNSUPPORTED: return "FNO_ERR_UNSUPPORTED: valid request beyond this implementation's limits";
+    case FNO_ERR_ALIGNMENT: return "FNO_ERR_ALIGNMENT: tensor pointer not 16-byte aligned";
+    case FNO_ERR_WORKSPACE: return "FNO_ERR_WORKSPACE: workspace or cache too small";
+    case FNO_ERR_HIP: return "FNO_ERR_HIP: HIP runtime or launch error";
+    case FNO_ERR_OOM: return "FNO_ERR_OOM: device allocation failed";
+    default: return "unknown fno status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// fno_internal.h -- shared definitions of the HIP library (plan layout,
+// kernel launcher prototypes, small device helpers).  Not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "fno_mi355x.h"
+
+namespace fno {
+
+// ---------------------------------------------------------------- plan
+// Basis tables live in device memory owned by the plan.  Every table is
+// generated in FP64 with the phase k*n reduced modulo N in 64-bit integers,
+// then rounded once to float.
+struct Tables {
+    // Per axis d = x, y, z, t: (cos, sin) of theta = 2*pi*((k_j n) mod N_d)/N_d,
+    // laid out [K_d][N_d] (retained index j major, grid point n minor).
+    float2 *cs[4];
+    // c(kt)/N per kt (weights of the real inverse transform) and ones.
+    float *wt_inv;
+    float *wt_one;
+};
+
+struct Dims {
+    int B, Ci, Co;
+    int N[4];  // Nx, Ny, Nz, Nt
+    int m[4];  // mx, my, mz, mt
+    int K[4];  // 2mx, 2my, 2mz, mt
+    long long ncell;      // Nx Ny Nz Nt
+    long long nmode;      // Kx Ky Kz Kt
+    long long plane;      // Nz Nt  (one (b, c, x, y) plane of an activation)
+    long long kplane;     // Kz Kt  (its truncated t, z spectrum)
+    long long P;          // Ky Kz Kt
+};
+
+}  // namespace fno
+
+struct fno_plan {
+    fno_desc_t desc;
+    fno::Dims d;
+    int device;
+    fno::Tables tab;
+    void *table_mem;
+};
+
+namespace fno {
+
+// Workspace carve-up shared by the host code of every entry point.
+struct Workspace {
+    float2 *t1;    // [B*C][Nx][Ny][Kz*Kt]  t,z spectrum (also its inverse-side twin)
+    float2 *t2;    // [B*C][Nx][Ky*Kz*Kt]   t,z,y spectrum
+    float2 *sp;    // [B*C][Kx*Ky*Kz*Kt]    retained spectrum (mix input or output)
+    float2 *sp2;   // [B*C][Kx*Ky*Kz*Kt]
+    float *gz;     // [B*Co][N]             gradient of the pre-activation (block bwd)
+    float *part;   // partial sums for the pointwise weight gradients
+    size_t bytes;
+};
+
+// ---------------------------------------------------------------- device helpers
+__device__ __forceinline__ float to_f32(float v) { return v; }
+__device__ __forceinline__ float to_f32(__bf16 v) { return (float)v; }
+template <typename T> __device__ __forceinline__ T from_f32(float v);
+template <> __device__ __forceinline__ float from_f32<float>(float v) { return v; }
+template <> __device__ __forceinline__ __bf16 from_f32<__bf16>(float v) { return (__bf16)v; }
+
+__device__ __forceinline__ float gelu_f(float u) { return 0.5f * u * (1.0f + erff(u * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float u)
+{
+    return 0.5f * (1.0f + erff(u * 0.70710678118654752f)) + u * 0.39894228040143268f * expf(-0.5f * u * u);
+}
+
+}  // namespace fno

@@ -1,0 +1,214 @@
+// mode_kernels.hip -- kernels that act on truncated spectra: one-axis complex
+// basis contractions (the x and y stages of the forward DFT, Alg. 2 line 1,
+// and of its inverse/adjoint, Alg. 2 line 3), the per-mode channel mix
+// (Alg. 2 line 2) and its gradients, and the deterministic reduction of the
+// pointwise-weight gradient partial sums.
+#include "fno_internal.h"
+
+namespace fno {
+
+// out[o][j][i] = sum_n E(j, n) in[o][n][i] along one axis of grid size N.
+//   forward (inverse == 0): j runs over retained frequencies (Nout = K), n over
+//     grid points (Nin = N), E = cos - i sin of tab[j][n]  (exp(-i theta));
+//   inverse (inverse != 0): j runs over grid points (Nout = N), n over retained
+//     frequencies (Nin = K), E = cos + i sin of tab[n][j]  (exp(+i theta)).
+// Thread per output element; inner (contiguous) index fastest across threads.
+__global__ void k_axis(const float2 *__restrict__ in, float2 *__restrict__ out, const float2 *__restrict__ tab,
+                       long long outer, int Nin, int Nout, long long inner, int N, int inverse)
+{
+    const long long total = outer * Nout * inner;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long i = e % inner;
+        const long long r = e / inner;
+        const int j = (int)(r % Nout);
+        const long long o = r / Nout;
+        const float2 *src = in + o * Nin * inner + i;
+        float re = 0.f, im = 0.f;
+        for (int n = 0; n < Nin; n++) {
+            const float2 c = inverse ? tab[(long long)n * N + j] : tab[(long long)j * N + n];
+            const float s = inverse ? c.y : -c.y;
+            const float2 v = src[(long long)n * inner];
+            re += c.x * v.x - s * v.y;
+            im += c.x * v.y + s * v.x;
+        }
+        out[e] = make_float2(re, im);
+    }
+}
+
+// Y^[b][o][k] = sum_i X^[b][i][k] W[i][o][k]
+__global__ void k_mix_fwd(const float2 *__restrict__ xh, const float2 *__restrict__ w, float2 *__restrict__ yh,
+                          int B, int Ci, int Co, long long M)
+{
+    const long long total = (long long)B * Co * M;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long k = e % M;
+        const long long r = e / M;
+        const int o = (int)(r % Co), b = (int)(r / Co);
+        float re = 0.f, im = 0.f;
+        for (int i = 0; i < Ci; i++) {
+            const float2 a = xh[((long long)b * Ci + i) * M + k];
+            const float2 q = w[((long long)i * Co + o) * M + k];
+            re += a.x * q.x - a.y * q.y;
+            im += a.x * q.y + a.y * q.x;
+        }
+        yh[e] = make_float2(re, im);
+    }
+}
+
+// gX^[b][i][k] = sum_o gY^[b][o][k] conj(W[i][o][k])
+__global__ void k_mix_bwd_x(const float2 *__restrict__ gyh, const float2 *__restrict__ w, float2 *__restrict__ gxh,
+                            int B, int Ci, int Co, long long M)
+{
+    const long long total = (long long)B * Ci * M;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long k = e % M;
+        const long long r = e / M;
+        const int i = (int)(r % Ci), b = (int)(r / Ci);
+        float re = 0.f, im = 0.f;
+        for (int o = 0; o < Co; o++) {
+            const float2 g = gyh[((long long)b * Co + o) * M + k];
+            const float2 q = w[((long long)i * Co + o) * M + k];
+            re += g.x * q.x + g.y * q.y;
+            im += g.y * q.x - g.x * q.y;
+        }
+        gxh[e] = make_float2(re, im);
+    }
+}
+
+// gW[i][o][k] (+)= sum_b conj(X^[b][i][k]) gY^[b][o][k]
+__global__ void k_mix_bwd_w(const float2 *__restrict__ xh, const float2 *__restrict__ gyh, float2 *__restrict__ gw,
+                            int B, int Ci, int Co, long long M, int accumulate)
+{
+    const long long total = (long long)Ci * Co * M;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long k = e % M;
+        const long long r = e / M;
+        const int o = (int)(r % Co), i = (int)(r / Co);
+        float re = 0.f, im = 0.f;
+        for (int b = 0; b < B; b++) {
+            const float2 a = xh[((long long)b * Ci + i) * M + k];
+            const float2 g = gyh[((long long)b * Co + o) * M + k];
+            re += a.x * g.x + a.y * g.y;
+            im += a.x * g.y - a.y * g.x;
+        }
+        if (accumulate) {
+            const float2 p = gw[e];
+            re += p.x;
+            im += p.y;
+        }
+        gw[e] = make_float2(re, im);
+    }
+}
+
+// Pointwise-weight gradient partials: for chunk c of the flat (b, n) range and
+// channel o, part[c][o][i] = sum gz[b][o][n] x[b][i][n] (i < Ci) and
+// part[c][o][Ci] = sum gz[b][o][n].  One workgroup per (chunk, o).
+template <typename T>
+__global__ void __launch_bounds__(256) k_pw_wgrad_partial(const float *__restrict__ gz, const T *__restrict__ x,
+                                                          float *__restrict__ part, int B, int Ci, int Co,
+                                                          long long ncell, long long chunk)
+{
+    constexpr int MAXC = 64;
+    const int o = blockIdx.y;
+    const long long c = blockIdx.x;
+    const long long total = (long long)B * ncell;
+    const long long beg = c * chunk;
+    const long long end = beg + chunk < total ? beg + chunk : total;
+    float acc[MAXC + 1];
+#pragma unroll
+    for (int i = 0; i <= MAXC; i++) acc[i] = 0.f;
+    for (long long e = beg + threadIdx.x; e < end; e += blockDim.x) {
+        const long long b = e / ncell, n = e % ncell;
+        const float g = gz[(b * Co + o) * ncell + n];
+        acc[MAXC] += g;
+#pragma unroll
+        for (int i = 0; i < MAXC; i++)
+            if (i < Ci) acc[i] += g * to_f32(x[(b * Ci + i) * ncell + n]);
+    }
+    __shared__ float red[256];
+#pragma unroll
+    for (int i = 0; i <= MAXC; i++) {
+        if (i <= Ci) {  // Ci is uniform across the workgroup
+            red[threadIdx.x] = (i == Ci) ? acc[MAXC] : acc[i];
+            __syncthreads();
+            for (int s = 128; s > 0; s >>= 1) {
+                if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) part[(c * Co + o) * (Ci + 1) + i] = red[0];
+            __syncthreads();
+        }
+    }
+}
+
+// gw_pw[o][i] (+)= sum_c part[c][o][i]; gb[o] (+)= sum_c part[c][o][Ci].  Fixed order.
+__global__ void k_pw_wgrad_reduce(const float *__restrict__ part, float *__restrict__ gwpw, float *__restrict__ gb,
+                                  int Ci, int Co, int nchunk, int accumulate)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= Co * (Ci + 1)) return;
+    const int o = e / (Ci + 1), i = e % (Ci + 1);
+    float s = 0.f;
+    for (int c = 0; c < nchunk; c++) s += part[((long long)c * Co + o) * (Ci + 1) + i];
+    if (i < Ci) {
+        if (gwpw) gwpw[o * Ci + i] = (accumulate ? gwpw[o * Ci + i] : 0.f) + s;
+    } else {
+        if (gb) gb[o] = (accumulate ? gb[o] : 0.f) + s;
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+static inline int grid_for(long long total, int block)
+{
+    long long g = (total + block - 1) / block;
+    if (g > 1048576) g = 1048576;
+    return (int)(g < 1 ? 1 : g);
+}
+
+void launch_axis(const float2 *in, float2 *out, const float2 *tab, long long outer, int Nin, int Nout,
+                 long long inner, int N, int inverse, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_axis, dim3(grid_for(outer * Nout * inner, 256)), dim3(256), 0, st, in, out, tab, outer, Nin,
+                       Nout, inner, N, inverse);
+}
+
+void launch_mix_fwd(const float2 *xh, const float2 *w, float2 *yh, int B, int Ci, int Co, long long M, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mix_fwd, dim3(grid_for((long long)B * Co * M, 256)), dim3(256), 0, st, xh, w, yh, B, Ci, Co, M);
+}
+
+void launch_mix_bwd(const float2 *xh, const float2 *w, const float2 *gyh, float2 *gxh, float2 *gw, int B, int Ci,
+                    int Co, long long M, int accumulate, hipStream_t st)
+{
+    if (gxh)
+        hipLaunchKernelGGL(k_mix_bwd_x, dim3(grid_for((long long)B * Ci * M, 256)), dim3(256), 0, st, gyh, w, gxh, B,
+                           Ci, Co, M);
+    if (gw)
+        hipLaunchKernelGGL(k_mix_bwd_w, dim3(grid_for((long long)Ci * Co * M, 256)), dim3(256), 0, st, xh, gyh, gw, B,
+                           Ci, Co, M, accumulate);
+}
+
+int pw_wgrad_chunks(long long total) { return (int)((total + 65535) / 65536); }
+
+template <typename T>
+void launch_pw_wgrad(const float *gz, const T *x, float *part, float *gwpw, float *gb, int B, int Ci, int Co,
+                     long long ncell, int accumulate, hipStream_t st)
+{
+    const long long total = (long long)B * ncell;
+    const long long chunk = 65536;
+    const int nchunk = pw_wgrad_chunks(total);
+    hipLaunchKernelGGL(k_pw_wgrad_partial<T>, dim3(nchunk, Co), dim3(256), 0, st, gz, x, part, B, Ci, Co, ncell, chunk);
+    hipLaunchKernelGGL(k_pw_wgrad_reduce, dim3((Co * (Ci + 1) + 255) / 256), dim3(256), 0, st, part, gwpw, gb, Ci, Co,
+                       nchunk, accumulate);
+}
+
+template void launch_pw_wgrad<float>(const float *, const float *, float *, float *, float *, int, int, int, long long,
+                                     int, hipStream_t);
+template void launch_pw_wgrad<__bf16>(const float *, const __bf16 *, float *, float *, float *, int, int, int,
+                                      long long, int, hipStream_t);
+
+}  // namespace fno

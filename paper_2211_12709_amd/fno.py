@@ -1,0 +1,248 @@
+"""Python binding of libfno_mi355x.so (C-ABI in include/fno_mi355x.h).
+
+Argument marshalling only: every arithmetic step of the spectral block runs
+in the HIP library.  PyTorch provides device memory and the current stream.
+Importing this module loads the library and raises if it is not built.
+
+Names follow the C entry points:
+    Plan(...).spectral_fwd / spectral_bwd / block_fwd / block_bwd
+and torch.autograd.Function wrappers SpectralConv4dFn and FNOBlockFn
+(the FNO block of arXiv 2211.12709, Alg. 1 and Alg. 2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfno_mi355x.so")
+
+FNO_OK, FNO_ERR_INVALID_ARG, FNO_ERR_UNSUPPORTED, FNO_ERR_ALIGNMENT, FNO_ERR_WORKSPACE, FNO_ERR_HIP, FNO_ERR_OOM = range(7)
+FNO_F32, FNO_BF16 = 0, 1
+OP_SPECTRAL_FWD, OP_SPECTRAL_BWD, OP_BLOCK_FWD, OP_BLOCK_BWD = range(4)
+
+EXPORTS = ("fno_desc_validate", "fno_plan_create", "fno_plan_destroy", "fno_workspace_bytes", "fno_cache_bytes",
+           "fno_spectral_fwd", "fno_spectral_bwd", "fno_block_fwd", "fno_block_bwd", "fno_status_str")
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("B", ctypes.c_int32), ("C_in", ctypes.c_int32), ("C_out", ctypes.c_int32),
+                ("grid", ctypes.c_int32 * 4), ("modes", ctypes.c_int32 * 4),
+                ("dtype", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class FnoError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {status_str(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library (no GPU needed to load it)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run __graft_entry__.build() (hipcc, gfx950) first")
+    L = ctypes.CDLL(path)
+    L.fno_desc_validate.argtypes = [ctypes.POINTER(Desc)]
+    L.fno_plan_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(Desc)]
+    L.fno_plan_destroy.argtypes = [_vp]
+    L.fno_workspace_bytes.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_sz)]
+    L.fno_cache_bytes.argtypes = [_vp, ctypes.POINTER(_sz)]
+    L.fno_spectral_fwd.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+    L.fno_spectral_bwd.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _sz, _vp]
+    L.fno_block_fwd.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+    L.fno_block_bwd.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _sz, _vp]
+    L.fno_status_str.argtypes = [ctypes.c_int]
+    L.fno_status_str.restype = ctypes.c_char_p
+    for f in EXPORTS[:-1]:
+        getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def status_str(code: int) -> str:
+    return load_library().fno_status_str(int(code)).decode()
+
+
+def _check(code, what):
+    if code != FNO_OK:
+        raise FnoError(code, what)
+
+
+def make_desc(B, C_in, C_out, grid, modes, dtype=FNO_F32, flags=0) -> Desc:
+    d = Desc()
+    d.B, d.C_in, d.C_out = B, C_in, C_out
+    d.grid[:] = list(grid)
+    d.modes[:] = list(modes)
+    d.dtype = dtype
+    d.flags = flags
+    return d
+
+
+def validate(desc: Desc) -> int:
+    return load_library().fno_desc_validate(ctypes.byref(desc))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+_TORCH_DTYPE = {FNO_F32: torch.float32, FNO_BF16: torch.bfloat16}
+
+
+class Plan:
+    """A plan for one block shape: basis tables on the current device."""
+
+    def __init__(self, B, C_in, C_out, grid, modes, dtype=FNO_F32):
+        L = load_library()
+        self.desc = make_desc(B, C_in, C_out, grid, modes, dtype)
+        self.B, self.C_in, self.C_out = B, C_in, C_out
+        self.grid, self.modes, self.dtype = tuple(grid), tuple(modes), dtype
+        self.kshape = (2 * modes[0], 2 * modes[1], 2 * modes[2], modes[3])
+        self.act_dtype = _TORCH_DTYPE[dtype]
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        h = _vp()
+        _check(L.fno_plan_create(ctypes.byref(h), ctypes.byref(self.desc)), "fno_plan_create")
+        self._h = h
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.fno_plan_destroy(h)
+            self._h = None
+
+    # ---------------------------------------------------------------- sizes
+    def workspace_bytes(self, op):
+        n = _sz()
+        _check(_lib.fno_workspace_bytes(self._h, op, ctypes.byref(n)), "fno_workspace_bytes")
+        return n.value
+
+    def cache_bytes(self):
+        n = _sz()
+        _check(_lib.fno_cache_bytes(self._h, ctypes.byref(n)), "fno_cache_bytes")
+        return n.value
+
+    def workspace(self, op):
+        """A reusable workspace for `op` (one per plan and op; reused across calls on the current stream)."""
+        n = self.workspace_bytes(op)
+        ws = self._ws.get(op)
+        if ws is None or ws.numel() < n:
+            ws = torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
+            self._ws[op] = ws
+        return ws
+
+    def new_cache(self):
+        return torch.empty(self.cache_bytes(), dtype=torch.uint8, device=self.device)
+
+    def act_shape(self, C):
+        return (self.B, C, *self.grid)
+
+    # ---------------------------------------------------------------- calls
+    def spectral_fwd(self, x, w, y=None, cache=None):
+        if y is None:
+            y = torch.empty(self.act_shape(self.C_out), dtype=self.act_dtype, device=self.device)
+        ws = self.workspace(OP_SPECTRAL_FWD)
+        _check(_lib.fno_spectral_fwd(self._h, _ptr(x), _ptr(w), _ptr(y), _ptr(cache), _ptr(ws), ws.numel(),
+                                     _stream()), "fno_spectral_fwd")
+        return y
+
+    def spectral_bwd(self, gy, w, x=None, cache=None, gx=None, gw=None, need_gx=True, need_gw=True, accumulate=False):
+        if need_gx and gx is None:
+            gx = torch.empty(self.act_shape(self.C_in), dtype=self.act_dtype, device=self.device)
+        if need_gw and gw is None:
+            gw = torch.empty((self.C_in, self.C_out, *self.kshape), dtype=torch.complex64, device=self.device)
+        ws = self.workspace(OP_SPECTRAL_BWD)
+        _check(_lib.fno_spectral_bwd(self._h, _ptr(x), _ptr(cache), _ptr(w), _ptr(gy), _ptr(gx if need_gx else None),
+                                     _ptr(gw if need_gw else None), int(accumulate), _ptr(ws), ws.numel(), _stream()),
+               "fno_spectral_bwd")
+        return gx, gw
+
+    def block_fwd(self, x, w, w_pw, b_pw=None, y=None, cache=None):
+        if y is None:
+            y = torch.empty(self.act_shape(self.C_out), dtype=self.act_dtype, device=self.device)
+        ws = self.workspace(OP_BLOCK_FWD)
+        _check(_lib.fno_block_fwd(self._h, _ptr(x), _ptr(w), _ptr(w_pw), _ptr(b_pw), _ptr(y), _ptr(cache), _ptr(ws),
+                                  ws.numel(), _stream()), "fno_block_fwd")
+        return y
+
+    def block_bwd(self, x, cache, w, w_pw, b_pw, gy, gx=None, gw=None, gw_pw=None, gb_pw=None, need_gw=True,
+                  need_gw_pw=True, need_gb=True, accumulate=False):
+        if gx is None:
+            gx = torch.empty(self.act_shape(self.C_in), dtype=self.act_dtype, device=self.device)
+        if need_gw and gw is None:
+            gw = torch.empty((self.C_in, self.C_out, *self.kshape), dtype=torch.complex64, device=self.device)
+        if need_gw_pw and gw_pw is None:
+            gw_pw = torch.empty((self.C_out, self.C_in), dtype=torch.float32, device=self.device)
+        if need_gb and gb_pw is None:
+            gb_pw = torch.empty((self.C_out,), dtype=torch.float32, device=self.device)
+        ws = self.workspace(OP_BLOCK_BWD)
+        _check(_lib.fno_block_bwd(self._h, _ptr(x), _ptr(cache), _ptr(w), _ptr(w_pw), _ptr(b_pw), _ptr(gy), _ptr(gx),
+                                  _ptr(gw if need_gw else None), _ptr(gw_pw if need_gw_pw else None),
+                                  _ptr(gb_pw if need_gb else None), int(accumulate), _ptr(ws), ws.numel(), _stream()),
+               "fno_block_bwd")
+        return gx, gw, gw_pw, gb_pw
+
+
+def _c(t):
+    return t if t.is_contiguous() else t.contiguous()
+
+
+class SpectralConv4dFn(torch.autograd.Function):
+    """y = spectral convolution of x with complex weights w (Alg. 2)."""
+
+    @staticmethod
+    def forward(ctx, x, w, plan: Plan):
+        x, w = _c(x), _c(w)
+        cache = plan.new_cache()
+        y = plan.spectral_fwd(x, w, cache=cache)
+        ctx.plan = plan
+        ctx.save_for_backward(x, w, cache)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, w, cache = ctx.saved_tensors
+        plan = ctx.plan
+        gx, gw = plan.spectral_bwd(_c(gy.to(plan.act_dtype)), w, x=x, cache=cache,
+                                   need_gx=ctx.needs_input_grad[0], need_gw=ctx.needs_input_grad[1])
+        return gx, gw, None
+
+
+class FNOBlockFn(torch.autograd.Function):
+    """y = GELU(spectral(x, w) + w_pw x + b_pw) with per-block recomputation:
+    only x and the small forward cache are kept for the backward."""
+
+    @staticmethod
+    def forward(ctx, x, w, w_pw, b_pw, plan: Plan):
+        x, w, w_pw = _c(x), _c(w), _c(w_pw)
+        b_pw = _c(b_pw) if b_pw is not None else None
+        cache = plan.new_cache()
+        y = plan.block_fwd(x, w, w_pw, b_pw, cache=cache)
+        ctx.plan = plan
+        ctx.has_bias = b_pw is not None
+        ctx.save_for_backward(x, w, w_pw, b_pw if b_pw is not None else torch.empty(0, device=x.device), cache)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, w, w_pw, b_pw, cache = ctx.saved_tensors
+        plan = ctx.plan
+        gx, gw, gwpw, gb = plan.block_bwd(x, cache, w, w_pw, b_pw if ctx.has_bias else None,
+                                          _c(gy.to(plan.act_dtype)), need_gw=ctx.needs_input_grad[1],
+                                          need_gw_pw=ctx.needs_input_grad[2],
+                                          need_gb=ctx.has_bias and ctx.needs_input_grad[3])
+        return gx, gw, gwpw, (gb if ctx.has_bias else None), None
