@@ -1,0 +1,265 @@
+"""Benchmark: FNO block forward + backward on one MI355X.
+
+A step is one pass of the whole hot path over one batch: fno_block_fwd
+(truncated forward DFT over t, z, y, x; per-mode channel mix; inverse DFT;
+fused pointwise 1x1 + bias + GELU) followed by fno_block_bwd (recomputation
+of the pre-activation, GELU gradient, pointwise gradients, spectral adjoint
+and complex weight gradient).
+
+Workload (default): the CO2-flow-shaped block of arXiv 2211.12709 Sec. V-B
+at grid 128^3 x 32, batch 1, width 20, modes 16,16,16,8.  The block input and
+the upstream gradient are smooth seeded synthetic fields
+(paper_2211_12709_amd.inputs.smooth_spacetime_field); weights are seeded.
+
+The BF16 path (bfloat16 activations, FP32 accumulation) is the reported value;
+the FP32 path runs the same kernels in float32 for the ratio.  Relative L2
+errors of y, gx, gw, gw_pw and gb against the FP64 CPU oracle are measured at
+the full size in the same run; that oracle run is also the cpu_baseline.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+WORKLOADS = {
+    # name: (B, C, grid, modes)
+    "co2_block_128^3x32": (1, 20, (128, 128, 128, 32), (16, 16, 16, 8)),
+    "ns_block_64^3x16": (1, 20, (64, 64, 64, 16), (12, 12, 12, 8)),
+    "co2_batched_block_128^3x32": (4, 32, (128, 128, 128, 32), (20, 20, 20, 10)),
+    "single_layer_16^3x8": (1, 8, (16, 16, 16, 8), (4, 4, 4, 4)),
+}
+
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
+METRIC = "FNO block fwd+bwd ms/step & TFLOP/s, BF16 vs FP32 at stated rel err"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------------ work model
+def flop_model(B, Ci, Co, grid, modes):
+    """Model flops of the block (truncated separable DFT, counted per stage)."""
+    nx, ny, nz, nt = grid
+    mx, my, mz, mt = modes
+    N = nx * ny * nz * nt
+    M = (2 * mx) * (2 * my) * (2 * mz) * mt
+
+    def dft(C):
+        t = 4 * B * C * N * mt
+        z = 8 * B * C * nx * ny * mt * nz * 2 * mz
+        y = 8 * B * C * nx * 2 * mz * mt * ny * 2 * my
+        x = 8 * B * C * 2 * my * 2 * mz * mt * nx * 2 * mx
+        return t + z + y + x, (t, z, y, x)
+
+    dft_in, _ = dft(Ci)
+    dft_out, stages = dft(Co)
+    mix = 8 * B * Ci * Co * M
+    pw = 2 * B * Ci * Co * N
+    fwd = dft_in + mix + dft_out + pw
+    bwd = dft_out + 2 * mix + dft_in + 2 * pw
+    recompute = (stages[2] + stages[3]) + (stages[0] + stages[1]) + pw
+    return dict(fwd=fwd, bwd=bwd, recompute=recompute, stages_t_z_y_x=stages, mix=mix, pointwise=pw)
+
+
+def kernel_model(name, B, Ci, Co, grid, modes, act_bytes):
+    """Algorithmic HBM bytes and flops of one launch of a kernel, counting what
+    the kernel has to read and write across its boundary."""
+    nx, ny, nz, nt = grid
+    mx, my, mz, mt = modes
+    N = nx * ny * nz * nt
+    C = Co  # block runs here have Ci == Co
+    A = B * C * N * act_bytes
+    kplane = B * C * nx * ny * (2 * mz) * mt * 8           # t,z spectrum (complex64)
+    t_fl = 4 * B * C * N * mt
+    z_fl = 8 * B * C * nx * ny * mt * nz * 2 * mz
+    pw = 2 * B * Ci * Co * N
+    if name.startswith("fwd_tz"):
+        a = A if "bf16" in name else B * C * N * 4
+        return dict(bytes=a + kplane, flops=t_fl + z_fl, unit="plane", units=B * C * nx * ny)
+    if name == "inv_zt_block":
+        return dict(bytes=kplane + 2 * A, flops=t_fl + z_fl + pw, unit="plane", units=B * nx * ny)
+    if name == "bwd_gz":
+        return dict(bytes=kplane + 2 * A + B * Co * N * 4, flops=t_fl + z_fl + pw, unit="plane", units=B * nx * ny)
+    if name == "inv_zt_adj":
+        return dict(bytes=kplane + B * Co * N * 4 + A, flops=t_fl + z_fl + pw, unit="plane", units=B * nx * ny)
+    return None
+
+
+# ------------------------------------------------------------------ helpers
+def rel(a, ref):
+    return float(np.linalg.norm((a - ref).ravel()) / max(np.linalg.norm(ref.ravel()), 1e-300))
+
+
+def run_gpu(args, wl):
+    import torch
+
+    from paper_2211_12709_amd import fno, inputs
+
+    B, C, grid, modes = wl
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    ksh = (2 * modes[0], 2 * modes[1], 2 * modes[2], modes[3])
+    log(f"[bench] generating inputs B={B} C={C} grid={grid} modes={modes}")
+    x = inputs.smooth_spacetime_field(B, C, grid, seed=inputs.SEED_INPUT)
+    gy = inputs.smooth_spacetime_field(B, C, grid, seed=inputs.SEED_TARGET)
+    w, wpw, bpw = inputs.block_params(C, C, ksh, block=0)
+    tw, twp, tb = (torch.from_numpy(a).to(dev) for a in (w, wpw, bpw))
+    x32 = torch.from_numpy(x).to(dev)
+    gy32 = torch.from_numpy(gy).to(dev)
+    results = {}
+    outputs = {}
+    for dt_name, code in (("bf16", fno.FNO_BF16), ("f32", fno.FNO_F32)):
+        if dt_name == "f32" and args.no_fp32:
+            continue
+        plan = fno.Plan(B, C, C, grid, modes, code)
+        xa = x32.to(plan.act_dtype).contiguous()
+        gya = gy32.to(plan.act_dtype).contiguous()
+        cache = plan.new_cache()
+        y = torch.empty_like(xa)
+        gx = torch.empty_like(xa)
+        gw = torch.empty((C, C, *ksh), dtype=torch.complex64, device=dev)
+        gwpw = torch.empty((C, C), dtype=torch.float32, device=dev)
+        gb = torch.empty((C,), dtype=torch.float32, device=dev)
+
+        def step():
+            plan.block_fwd(xa, tw, twp, tb, y=y, cache=cache)
+            plan.block_bwd(xa, cache, tw, twp, tb, gya, gx=gx, gw=gw, gw_pw=gwpw, gb_pw=gb)
+
+        log(f"[bench] {dt_name}: warmup {args.warmup}")
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        plan.timing(True)
+        plan.timing_read()
+        log(f"[bench] {dt_name}: timing {args.steps} steps")
+        stream = torch.cuda.current_stream()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        plan.timing(False)
+        kern = plan.timing_read()
+        ms = ev0.elapsed_time(ev1) / args.steps
+        results[dt_name] = dict(ms=ms, wall_ms=wall * 1000 / args.steps, kernels=kern)
+        log(f"[bench] {dt_name}: {ms:.3f} ms/step")
+        if not args.no_oracle:
+            outputs[dt_name] = dict(y=y.float().cpu().numpy(), gx=gx.float().cpu().numpy(),
+                                    gw=gw.cpu().numpy(), gw_pw=gwpw.cpu().numpy(), gb=gb.cpu().numpy())
+        del plan, xa, gya, cache, y, gx
+        torch.cuda.empty_cache()
+    return results, outputs, (x, gy, w, wpw, bpw)
+
+
+def run_oracle(wl, data):
+    from oracle import oracle as o
+    B, C, grid, modes = wl
+    x, gy, w, wpw, bpw = data
+    d = o.Dims(B, C, C, grid, modes)
+    log("[bench] oracle (FP64 CPU) block fwd+bwd")
+    t0 = time.perf_counter()
+    y = o.block_fwd(d, x, w, wpw, bpw)
+    gx, gw, gwpw, gb = o.block_bwd(d, x, w, wpw, bpw, gy)
+    sec = time.perf_counter() - t0
+    log(f"[bench] oracle: {sec:.1f} s")
+    return dict(y=y, gx=gx, gw=gw, gw_pw=gwpw, gb=gb), sec
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="co2_block_128^3x32", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-oracle", action="store_true", help="skip the FP64 oracle (errors and cpu_baseline)")
+    ap.add_argument("--no-fp32", action="store_true", help="time the BF16 path only")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    if int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs as a single process on one GPU.", file=sys.stderr)
+        sys.exit(2)
+
+    wl = WORKLOADS[args.workload]
+    B, C, grid, modes = wl
+    fm = flop_model(B, C, C, grid, modes)
+    model_flops = fm["fwd"] + fm["bwd"]
+    results, outputs, data = run_gpu(args, wl)
+
+    errs, cpu = {}, None
+    if not args.no_oracle:
+        ref, sec = run_oracle(wl, data)
+        for dt_name, out in outputs.items():
+            errs[dt_name] = {k: rel(np.asarray(out[k], dtype=ref[k].dtype), ref[k]) for k in ref}
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        cpu = dict(value=model_flops / sec / 1e12, unit="TFLOP/s", cores=threads, kind="oracle",
+                   sample=f"one full block fwd+bwd of the benchmark workload ({args.workload}), FP64, "
+                          f"{sec:.1f} s wall")
+
+    bf = results["bf16"]
+    ms = bf["ms"]
+    value = model_flops / (ms * 1e-3) / 1e12
+    # dominant kernel of the BF16 step and its roofline
+    kern = bf["kernels"]
+    dom = max(kern.items(), key=lambda kv: kv[1][1])
+    name, (launches, tot_ms) = dom
+    avg_ms = tot_ms / launches
+    km = kernel_model(name, B, C, C, grid, modes, 2)
+    roof = None
+    if km is not None:
+        t_hbm = km["bytes"] / (HBM_PEAK_GBS * 1e9)
+        t_mfma = km["flops"] / (MFMA_PEAK_TFLOPS["bf16"] * 1e12)
+        if t_hbm >= t_mfma:
+            ach = km["bytes"] / (avg_ms * 1e-3) / 1e9
+            roof = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                        traffic=None, kernel=name, avg_ms=avg_ms, bytes_per_launch=km["bytes"])
+        else:
+            ach = km["flops"] / (avg_ms * 1e-3) / 1e12
+            roof = dict(bound="mfma", achieved=ach, peak=MFMA_PEAK_TFLOPS["bf16"], unit="TFLOP/s",
+                        frac=ach / MFMA_PEAK_TFLOPS["bf16"], traffic=None, kernel=name, avg_ms=avg_ms)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "batch": B, "width": C, "grid": list(grid), "modes": list(modes)},
+        "fp32_ms_per_step": results.get("f32", {}).get("ms"),
+        "bf16_speedup_vs_fp32": (results["f32"]["ms"] / ms) if "f32" in results else None,
+        "model_gflop_per_step": model_flops / 1e9,
+        "rel_l2_vs_fp64_oracle": errs or None,
+        "kernels_ms_per_step": {dt: {k: v[1] / args.steps for k, v in r["kernels"].items()} for dt, r in results.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

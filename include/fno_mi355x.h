@@ -129,6 +129,15 @@ int fno_block_bwd(const fno_plan_t *plan, const void *x, const void *cache, cons
                   const void *w_pw, const void *b_pw, const void *gy, void *gx, void *gw,
                   void *gw_pw, void *gb_pw, int accumulate, void *ws, size_t ws_bytes, void *stream);
 
+/* Per-kernel timing (diagnostic, for benchmarks and profiles).  While enabled
+ * on a plan, every kernel the plan launches is bracketed by two HIP events
+ * recorded on the launch stream.  fno_timing_read waits for the recorded
+ * events, writes a NUL-terminated JSON object {"kernel": [launches, total_ms],
+ * ...} into buf (FNO_ERR_WORKSPACE if buf_bytes is too small) and clears the
+ * records.  Not thread-safe: enable it only where one thread drives the plan. */
+int fno_timing_enable(fno_plan_t *plan, int enable);
+int fno_timing_read(fno_plan_t *plan, char *buf, size_t buf_bytes);
+
 /* Static description of a status code. */
 const char *fno_status_str(int status);
 

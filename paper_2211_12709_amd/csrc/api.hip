@@ -8,7 +8,10 @@
 //   mix:               Y^ = X^ W per retained mode
 //   inverse:           Y^ -x-> U2 -y-> U1 -z,t + epilogue-> output
 #include <algorithm>
+#include <cstdio>
+#include <cstring>
 #include <new>
+#include <string>
 
 #include "fno_internal.h"
 
@@ -43,6 +46,54 @@ static const int kMaxChannels = 64;
 static const size_t kMaxLds = 65536;
 
 static size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Brackets one kernel launch with events when the plan's timing is enabled.
+class KernelTimer {
+  public:
+    KernelTimer(const fno_plan_t *p, const char *name, hipStream_t st) : p_(p), name_(name), st_(st)
+    {
+        if (p_->timing.on) {
+            start_ = take();
+            (void)hipEventRecord(start_, st_);
+        }
+    }
+    ~KernelTimer()
+    {
+        if (p_->timing.on) {
+            hipEvent_t stop = take();
+            (void)hipEventRecord(stop, st_);
+            p_->timing.recs.push_back({name_, start_, stop});
+        }
+    }
+
+  private:
+    hipEvent_t take()
+    {
+        auto &pool = p_->timing.pool;
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    const fno_plan_t *p_;
+    const char *name_;
+    hipStream_t st_;
+    hipEvent_t start_ = nullptr;
+};
+
+#define FNO_TIMED(p, st, name, call) \
+    do {                             \
+        KernelTimer _kt(p, name, st); \
+        call;                        \
+    } while (0)
+
+template <typename T> static const char *tname();
+template <> const char *tname<float>() { return "f32"; }
+template <> const char *tname<__bf16>() { return "bf16"; }
 
 static int dims_from_desc(const fno_desc_t *s, Dims *d)
 {
@@ -127,9 +178,12 @@ static void forward_spectrum(const fno_plan_t *p, const T *in, int C, const floa
                              float2 *xh, hipStream_t st)
 {
     const Dims &d = p->d;
-    launch_fwd_tz<T>(in, t1, (long long)d.B * C * d.N[0] * d.N[1], d, p->tab, wt, st);
-    launch_axis(t1, t2, p->tab.cs[1], (long long)d.B * C * d.N[0], d.N[1], d.K[1], d.kplane, d.N[1], 0, st);
-    launch_axis(t2, xh, p->tab.cs[0], (long long)d.B * C, d.N[0], d.K[0], d.P, d.N[0], 0, st);
+    FNO_TIMED(p, st, tname<T>()[0] == 'b' ? "fwd_tz<bf16>" : "fwd_tz<f32>",
+              launch_fwd_tz<T>(in, t1, (long long)d.B * C * d.N[0] * d.N[1], d, p->tab, wt, st));
+    FNO_TIMED(p, st, "axis_fwd_y",
+              launch_axis(t1, t2, p->tab.cs[1], (long long)d.B * C * d.N[0], d.N[1], d.K[1], d.kplane, d.N[1], 0, st));
+    FNO_TIMED(p, st, "axis_fwd_x",
+              launch_axis(t2, xh, p->tab.cs[0], (long long)d.B * C, d.N[0], d.K[0], d.P, d.N[0], 0, st));
 }
 
 // Inverse x then y stage of a retained spectrum (C channels): spec -> u2 -> u1.
@@ -137,8 +191,11 @@ static void inverse_xy(const fno_plan_t *p, const float2 *spec, int C, float2 *u
                        bool skip_x = false)
 {
     const Dims &d = p->d;
-    if (!skip_x) launch_axis(spec, u2, p->tab.cs[0], (long long)d.B * C, d.K[0], d.N[0], d.P, d.N[0], 1, st);
-    launch_axis(u2, u1, p->tab.cs[1], (long long)d.B * C * d.N[0], d.K[1], d.N[1], d.kplane, d.N[1], 1, st);
+    if (!skip_x)
+        FNO_TIMED(p, st, "axis_inv_x",
+                  launch_axis(spec, u2, p->tab.cs[0], (long long)d.B * C, d.K[0], d.N[0], d.P, d.N[0], 1, st));
+    FNO_TIMED(p, st, "axis_inv_y",
+              launch_axis(u2, u1, p->tab.cs[1], (long long)d.B * C * d.N[0], d.K[1], d.N[1], d.kplane, d.N[1], 1, st));
 }
 
 template <typename T>
@@ -161,10 +218,11 @@ static int spectral_or_block_fwd(const fno_plan_t *p, const void *x_, const void
     float2 *yh = (float2 *)(wb + wp.sp2);
     const T *x = (const T *)x_;
     forward_spectrum<T>(p, x, d.Ci, p->tab.wt_one, t1, t2, xh, st);
-    launch_mix_fwd(xh, (const float2 *)w_, yh, d.B, d.Ci, d.Co, d.nmode, st);
+    FNO_TIMED(p, st, "mix_fwd", launch_mix_fwd(xh, (const float2 *)w_, yh, d.B, d.Ci, d.Co, d.nmode, st));
     inverse_xy(p, yh, d.Co, u2, t1, st);
-    launch_inv_zt<T>(block ? EPI_BLOCK : EPI_PLAIN, t1, (T *)y_, d.Co, d, p->tab, p->tab.wt_inv, x,
-                     (const float *)wpw, (const float *)bpw, nullptr, d.Ci, 0, st);
+    FNO_TIMED(p, st, block ? "inv_zt_block" : "inv_zt_plain",
+              launch_inv_zt<T>(block ? EPI_BLOCK : EPI_PLAIN, t1, (T *)y_, d.Co, d, p->tab, p->tab.wt_inv, x,
+                               (const float *)wpw, (const float *)bpw, nullptr, d.Ci, 0, st));
     return finish();
 }
 
@@ -196,12 +254,14 @@ static int spectral_bwd_impl(const fno_plan_t *p, const void *x_, const void *ca
     }
     // adjoint of the real inverse: gY^ = (c(kt)/N) sum_n gy exp(-i theta)
     forward_spectrum<T>(p, (const T *)gy_, d.Co, p->tab.wt_inv, t1, t2, gyh, st);
-    launch_mix_bwd(xh, (const float2 *)w_, gyh, gx_ ? gxh : nullptr, (float2 *)gw_, d.B, d.Ci, d.Co, d.nmode,
-                   accumulate, st);
+    FNO_TIMED(p, st, "mix_bwd",
+              launch_mix_bwd(xh, (const float2 *)w_, gyh, gx_ ? gxh : nullptr, (float2 *)gw_, d.B, d.Ci, d.Co,
+                             d.nmode, accumulate, st));
     if (gx_) {
         inverse_xy(p, gxh, d.Ci, t2, t1, st);
-        launch_inv_zt<T>(EPI_ADJ, t1, (T *)gx_, d.Ci, d, p->tab, p->tab.wt_one, nullptr, nullptr, nullptr, nullptr,
-                         d.Co, accumulate, st);
+        FNO_TIMED(p, st, "inv_zt_adj",
+                  launch_inv_zt<T>(EPI_ADJ, t1, (T *)gx_, d.Ci, d, p->tab, p->tab.wt_one, nullptr, nullptr, nullptr,
+                                   nullptr, d.Co, accumulate, st));
     }
     return finish();
 }
@@ -230,14 +290,20 @@ static int block_bwd_impl(const fno_plan_t *p, const void *x_, const void *cache
     const float *wpw = (const float *)wpw_, *bpw = (const float *)bpw_;
     // recompute the pre-activation from the cached x-inverse of Y^, then gz
     inverse_xy(p, nullptr, d.Co, const_cast<float2 *>(u2), t1, st, true);
-    launch_bwd_gz<T>(t1, x, (const T *)gy_, gz, d, p->tab, wpw, bpw, st);
-    if (gwpw_ || gb_) launch_pw_wgrad<T>(gz, x, part, (float *)gwpw_, (float *)gb_, d.B, d.Ci, d.Co, d.ncell, accumulate, st);
+    FNO_TIMED(p, st, "bwd_gz", launch_bwd_gz<T>(t1, x, (const T *)gy_, gz, d, p->tab, wpw, bpw, st));
+    if (gwpw_ || gb_)
+        FNO_TIMED(p, st, "pw_wgrad",
+                  launch_pw_wgrad<T>(gz, x, part, (float *)gwpw_, (float *)gb_, d.B, d.Ci, d.Co, d.ncell, accumulate,
+                                     st));
     // spectral part: gY^ = (c/N) DFT(gz), then the mix gradients and the adjoint
     forward_spectrum<float>(p, gz, d.Co, p->tab.wt_inv, t1, t2, gyh, st);
-    launch_mix_bwd(xh, (const float2 *)w_, gyh, gxh, (float2 *)gw_, d.B, d.Ci, d.Co, d.nmode, accumulate, st);
+    FNO_TIMED(p, st, "mix_bwd",
+              launch_mix_bwd(xh, (const float2 *)w_, gyh, gxh, (float2 *)gw_, d.B, d.Ci, d.Co, d.nmode, accumulate,
+                             st));
     inverse_xy(p, gxh, d.Ci, t2, t1, st);
-    launch_inv_zt<T>(EPI_ADJ, t1, (T *)gx_, d.Ci, d, p->tab, p->tab.wt_one, nullptr, wpw, nullptr, gz, d.Co,
-                     accumulate, st);
+    FNO_TIMED(p, st, "inv_zt_adj",
+              launch_inv_zt<T>(EPI_ADJ, t1, (T *)gx_, d.Ci, d, p->tab, p->tab.wt_one, nullptr, wpw, nullptr, gz, d.Co,
+                               accumulate, st));
     return finish();
 }
 
@@ -287,6 +353,11 @@ int fno_plan_destroy(fno_plan_t *plan)
 {
     if (!plan) return FNO_ERR_INVALID_ARG;
     int rc = FNO_OK;
+    for (auto &r : plan->timing.recs) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    for (auto e : plan->timing.pool) (void)hipEventDestroy(e);
     if (plan->table_mem && hipFree(plan->table_mem) != hipSuccess) rc = FNO_ERR_HIP;
     delete plan;
     return rc;
@@ -347,6 +418,44 @@ int fno_block_bwd(const fno_plan_t *plan, const void *x, const void *cache, cons
                                       ws_bytes, stream);
     return block_bwd_impl<float>(plan, x, cache, w, w_pw, b_pw, gy, gx, gw, gw_pw, gb_pw, accumulate, ws, ws_bytes,
                                  stream);
+}
+
+int fno_timing_enable(fno_plan_t *plan, int enable)
+{
+    if (!plan) return FNO_ERR_INVALID_ARG;
+    plan->timing.on = enable != 0;
+    return FNO_OK;
+}
+
+int fno_timing_read(fno_plan_t *plan, char *buf, size_t buf_bytes)
+{
+    if (!plan || !buf || buf_bytes == 0) return FNO_ERR_INVALID_ARG;
+    Timing &t = plan->timing;
+    std::vector<std::pair<std::string, std::pair<long, double>>> agg;
+    int rc = FNO_OK;
+    for (auto &r : t.recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.stop) != hipSuccess || hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess)
+            rc = FNO_ERR_HIP;
+        bool found = false;
+        for (auto &a : agg)
+            if (a.first == r.name) { a.second.first += 1; a.second.second += ms; found = true; break; }
+        if (!found) agg.push_back({r.name, {1, (double)ms}});
+        t.pool.push_back(r.start);
+        t.pool.push_back(r.stop);
+    }
+    t.recs.clear();
+    std::string js = "{";
+    for (size_t i = 0; i < agg.size(); i++) {
+        char item[256];
+        snprintf(item, sizeof item, "%s\"%s\": [%ld, %.6f]", i ? ", " : "", agg[i].first.c_str(), agg[i].second.first,
+                 agg[i].second.second);
+        js += item;
+    }
+    js += "}";
+    if (js.size() + 1 > buf_bytes) return FNO_ERR_WORKSPACE;
+    memcpy(buf, js.c_str(), js.size() + 1);
+    return rc;
 }
 
 const char *fno_status_str(int status)

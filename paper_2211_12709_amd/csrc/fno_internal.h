@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "fno_mi355x.h"
 
 namespace fno {
@@ -37,12 +39,26 @@ struct Dims {
 
 }  // namespace fno
 
+namespace fno {
+// Opt-in per-kernel event timing of a plan's launches.
+struct TimingRec {
+    const char *name;
+    hipEvent_t start, stop;
+};
+struct Timing {
+    bool on = false;
+    std::vector<TimingRec> recs;
+    std::vector<hipEvent_t> pool;
+};
+}  // namespace fno
+
 struct fno_plan {
     fno_desc_t desc;
     fno::Dims d;
     int device;
     fno::Tables tab;
     void *table_mem;
+    mutable fno::Timing timing;
 };
 
 namespace fno {

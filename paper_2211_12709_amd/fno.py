@@ -24,7 +24,8 @@ FNO_F32, FNO_BF16 = 0, 1
 OP_SPECTRAL_FWD, OP_SPECTRAL_BWD, OP_BLOCK_FWD, OP_BLOCK_BWD = range(4)
 
 EXPORTS = ("fno_desc_validate", "fno_plan_create", "fno_plan_destroy", "fno_workspace_bytes", "fno_cache_bytes",
-           "fno_spectral_fwd", "fno_spectral_bwd", "fno_block_fwd", "fno_block_bwd", "fno_status_str")
+           "fno_spectral_fwd", "fno_spectral_bwd", "fno_block_fwd", "fno_block_bwd", "fno_timing_enable",
+           "fno_timing_read", "fno_status_str")
 
 
 class Desc(ctypes.Structure):
@@ -61,6 +62,8 @@ def load_library(path: str = LIB_PATH):
     L.fno_spectral_bwd.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _sz, _vp]
     L.fno_block_fwd.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
     L.fno_block_bwd.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _sz, _vp]
+    L.fno_timing_enable.argtypes = [_vp, ctypes.c_int]
+    L.fno_timing_read.argtypes = [_vp, ctypes.c_char_p, _sz]
     L.fno_status_str.argtypes = [ctypes.c_int]
     L.fno_status_str.restype = ctypes.c_char_p
     for f in EXPORTS[:-1]:
@@ -150,6 +153,17 @@ class Plan:
 
     def act_shape(self, C):
         return (self.B, C, *self.grid)
+
+    # ---------------------------------------------------------------- timing
+    def timing(self, enable: bool):
+        _check(_lib.fno_timing_enable(self._h, int(enable)), "fno_timing_enable")
+
+    def timing_read(self):
+        """{kernel: (launches, total_ms)} of the launches recorded since the last read."""
+        import json
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(_lib.fno_timing_read(self._h, buf, len(buf)), "fno_timing_read")
+        return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}
 
     # ---------------------------------------------------------------- calls
     def spectral_fwd(self, x, w, y=None, cache=None):

@@ -145,3 +145,27 @@ def block_params(ci, co, kshape, block=0):
     w = spectral_weights(ci, co, kshape, seed=SEED_SPECTRAL_W + block)
     wpw, bpw = linear_weights(co, ci, seed=SEED_POINTWISE + block)
     return w, wpw, bpw
+
+
+def smooth_spacetime_field(batch, channels, grid, seed, corr_len=16.0) -> np.ndarray:
+    """[batch, channels, Nx, Ny, Nz, Nt] float32 stand-in for a hidden FNO
+    activation on a CO2- or NS-shaped grid: per (b, c) two independent 3-D
+    Gaussian-covariance fields g1, g2 (correlation length corr_len cells) and
+    x = (g1 + g2 sin(2 pi f t / Nt + phi)) / sqrt(1.5), with f in {1, 2, 3} and
+    phi uniform, drawn from the seed.  Smooth in space, periodic in time, with
+    unit variance on average."""
+    nx, ny, nz, nt = grid
+    rng = np.random.default_rng(seed)
+    out = np.empty((batch, channels, nx, ny, nz, nt), dtype=np.float32)
+    t = np.arange(nt)
+    for b in range(batch):
+        for c in range(channels):
+            s1, s2 = (int(v) for v in rng.integers(0, 2 ** 31, size=2))
+            f = int(rng.integers(1, 4))
+            phi = float(rng.uniform(0, 2 * np.pi))
+            cl = min(corr_len, max(nx, ny, nz) / 8.0)
+            g1 = grf_gaussian_cov((nx, ny, nz), corr_len=cl, seed=s1).astype(np.float32)
+            g2 = grf_gaussian_cov((nx, ny, nz), corr_len=cl, seed=s2).astype(np.float32)
+            prof = np.sin(2 * np.pi * f * t / nt + phi).astype(np.float32)
+            out[b, c] = (g1[..., None] + g2[..., None] * prof) / np.float32(np.sqrt(1.5))
+    return out
