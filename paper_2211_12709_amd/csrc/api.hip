@@ -38,9 +38,21 @@ template <typename T>
 void launch_bwd_gz(const float2 *u, const T *x, const T *gy, float *gz, const Dims &d, const Tables &tab,
                    const float *wpw, const float *bpw, hipStream_t st);
 size_t fwd_tz_lds(const Dims &d);
+struct TabGeom;
+struct TzyTabs {
+    const void *t, *t_lo, *z, *z_lo, *y, *y_lo;
+};
+bool tzy_supported(const Dims &d, int dtype);
+template <typename T>
+hipError_t launch_tzy(const T *x, float2 *t2, long long slabs, const TzyTabs &tb, const Dims &d, hipStream_t st);
 size_t inv_zt_lds(const Dims &d);
 
 enum { EPI_PLAIN = 0, EPI_BLOCK = 1, EPI_ADJ = 2 };
+
+TabGeom *new_geom(const Dims &d, int dtype);
+void free_geom(TabGeom *g);
+long long tab_count(int kind, const TabGeom &G);
+void gen_frag(int kind, const TabGeom &G, const Tables::Frag &f, hipStream_t st);
 
 static const int kMaxChannels = 64;
 static const size_t kMaxLds = 65536;
@@ -174,14 +186,36 @@ static int finish()
 
 // X^ of activations `in` (C channels) into xh, using t1/t2 as scratch.
 template <typename T>
+static TzyTabs tzy_tabs(const fno_plan_t *p, const float *wt)
+{
+    const Tables &tb = p->tab;
+    const Tables::Frag &tt = (wt == tb.wt_inv) ? tb.t_bwd : tb.t_fwd;
+    TzyTabs r;
+    if (sizeof(T) == 2) {
+        r = {tt.hi, tt.lo, tb.z_fwd.hi, tb.z_fwd.lo, tb.y_fwd_bf16.hi, tb.y_fwd_bf16.lo};
+    } else {
+        r = {tt.f, nullptr, tb.z_fwd.f, nullptr, tb.y_fwd_f32.f, nullptr};
+    }
+    return r;
+}
+
+// X^ of activations `in` (C channels) into xh, using t1/t2 as scratch.
+// wt selects the t weights: wt_one (forward DFT) or wt_inv (c(kt)/N, adjoint of the real inverse).
+template <typename T>
 static void forward_spectrum(const fno_plan_t *p, const T *in, int C, const float *wt, float2 *t1, float2 *t2,
                              float2 *xh, hipStream_t st)
 {
     const Dims &d = p->d;
-    FNO_TIMED(p, st, tname<T>()[0] == 'b' ? "fwd_tz<bf16>" : "fwd_tz<f32>",
-              launch_fwd_tz<T>(in, t1, (long long)d.B * C * d.N[0] * d.N[1], d, p->tab, wt, st));
-    FNO_TIMED(p, st, "axis_fwd_y",
-              launch_axis(t1, t2, p->tab.cs[1], (long long)d.B * C * d.N[0], d.N[1], d.K[1], d.kplane, d.N[1], 0, st));
+    if (tzy_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
+        FNO_TIMED(p, st, sizeof(T) == 2 ? "tzy_fwd<bf16>" : "tzy_fwd<f32>",
+                  (void)launch_tzy<T>(in, t2, (long long)d.B * C * d.N[0], tzy_tabs<T>(p, wt), d, st));
+    } else {
+        FNO_TIMED(p, st, sizeof(T) == 2 ? "fwd_tz<bf16>" : "fwd_tz<f32>",
+                  launch_fwd_tz<T>(in, t1, (long long)d.B * C * d.N[0] * d.N[1], d, p->tab, wt, st));
+        FNO_TIMED(p, st, "axis_fwd_y",
+                  launch_axis(t1, t2, p->tab.cs[1], (long long)d.B * C * d.N[0], d.N[1], d.K[1], d.kplane, d.N[1], 0,
+                              st));
+    }
     FNO_TIMED(p, st, "axis_fwd_x",
               launch_axis(t2, xh, p->tab.cs[0], (long long)d.B * C, d.N[0], d.K[0], d.P, d.N[0], 0, st));
 }
@@ -331,16 +365,56 @@ int fno_plan_create(fno_plan_t **out, const fno_desc_t *desc)
     p->desc = *desc;
     p->d = d;
     if (hipGetDevice(&p->device) != hipSuccess) { delete p; return FNO_ERR_HIP; }
-    size_t off[6], tot = 0;
-    for (int a = 0; a < 4; a++) { off[a] = tot; tot += align_up(sizeof(float2) * (size_t)d.K[a] * d.N[a]); }
-    off[4] = tot; tot += align_up(sizeof(float) * d.K[3]);
-    off[5] = tot; tot += align_up(sizeof(float) * d.K[3]);
-    if (hipMalloc(&p->table_mem, tot) != hipSuccess) { (void)hipGetLastError(); delete p; return FNO_ERR_OOM; }
+    // basis tables: per-axis (cos, sin), inverse weights, and the MFMA fragment tables
+    TabGeom *G32 = new_geom(d, FNO_F32), *G16 = new_geom(d, FNO_BF16);
+    const long long n_t = tab_count(0, *G32), n_z = tab_count(2, *G32);
+    const long long n_y32 = tab_count(3, *G32), n_y16 = tab_count(3, *G16);
+    size_t off = 0;
+    size_t o_cs[4];
+    for (int a = 0; a < 4; a++) { o_cs[a] = off; off += align_up(sizeof(float2) * (size_t)d.K[a] * d.N[a]); }
+    const size_t o_wi = off; off += align_up(sizeof(float) * d.K[3]);
+    const size_t o_wo = off; off += align_up(sizeof(float) * d.K[3]);
+    auto frag_bytes = [](long long n) { return align_up(sizeof(float) * n) + 2 * align_up(sizeof(short) * n); };
+    const size_t o_tf = off; off += frag_bytes(n_t);
+    const size_t o_tb = off; off += frag_bytes(n_t);
+    const size_t o_zf = off; off += frag_bytes(n_z);
+    const size_t o_y32 = off; off += frag_bytes(n_y32);
+    const size_t o_y16 = off; off += frag_bytes(n_y16);
+    if (hipMalloc(&p->table_mem, off) != hipSuccess) {
+        (void)hipGetLastError();
+        free_geom(G32);
+        free_geom(G16);
+        delete p;
+        return FNO_ERR_OOM;
+    }
     char *base = (char *)p->table_mem;
-    for (int a = 0; a < 4; a++) p->tab.cs[a] = (float2 *)(base + off[a]);
-    p->tab.wt_inv = (float *)(base + off[4]);
-    p->tab.wt_one = (float *)(base + off[5]);
-    if (generate_tables(d, p->tab, nullptr) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    for (int a = 0; a < 4; a++) p->tab.cs[a] = (float2 *)(base + o_cs[a]);
+    p->tab.wt_inv = (float *)(base + o_wi);
+    p->tab.wt_one = (float *)(base + o_wo);
+    auto frag_at = [&](size_t o, long long n) {
+        Tables::Frag f;
+        f.f = (float *)(base + o);
+        f.hi = (short *)(base + o + align_up(sizeof(float) * n));
+        f.lo = (short *)(base + o + align_up(sizeof(float) * n) + align_up(sizeof(short) * n));
+        return f;
+    };
+    p->tab.t_fwd = frag_at(o_tf, n_t);
+    p->tab.t_bwd = frag_at(o_tb, n_t);
+    p->tab.z_fwd = frag_at(o_zf, n_z);
+    p->tab.y_fwd_f32 = frag_at(o_y32, n_y32);
+    p->tab.y_fwd_bf16 = frag_at(o_y16, n_y16);
+    hipError_t ge = generate_tables(d, p->tab, nullptr);
+    if (ge == hipSuccess) {
+        gen_frag(0, *G32, p->tab.t_fwd, nullptr);
+        gen_frag(1, *G32, p->tab.t_bwd, nullptr);
+        gen_frag(2, *G32, p->tab.z_fwd, nullptr);
+        gen_frag(3, *G32, p->tab.y_fwd_f32, nullptr);
+        gen_frag(3, *G16, p->tab.y_fwd_bf16, nullptr);
+        ge = hipGetLastError();
+    }
+    free_geom(G32);
+    free_geom(G16);
+    if (ge != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         (void)hipFree(p->table_mem);
         delete p;
         return FNO_ERR_HIP;

@@ -23,6 +23,14 @@ struct Tables {
     // c(kt)/N per kt (weights of the real inverse transform) and ones.
     float *wt_inv;
     float *wt_one;
+    // Fragment-ordered tables of the MFMA kernels (tables.hip): float copy and
+    // bfloat16 hi/lo split of each.  y tables exist for the float kernels'
+    // y chunk (16 planes) and the bfloat16 kernels' (32 planes).
+    struct Frag {
+        float *f;
+        short *hi, *lo;
+    };
+    Frag t_fwd, t_bwd, z_fwd, y_fwd_f32, y_fwd_bf16;
 };
 
 struct Dims {

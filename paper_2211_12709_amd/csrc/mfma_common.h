@@ -1,0 +1,76 @@
+// mfma_common.h -- fragment conventions shared by the MFMA kernels.
+//
+// All MFMA work uses 16x16 output tiles.  One "K chunk" is 16 deep: lane
+// l = 16 g + c (g = l / 16, c = l % 16) holds 4 consecutive K values
+// k = 16 q + 4 g + j (j = 0..3) of row c of the A tile and of column c of the
+// B tile.  For bfloat16 operands that is exactly one v_mfma_f32_16x16x16_bf16;
+// for float operands it is four v_mfma_f32_16x16x4_f32, the j-th one taking
+// value j of each lane (its K row g is then k = 16 q + 4 g + j, a fixed
+// permutation that A and B share, so the sum over k is unchanged).
+// An accumulator tile holds C[4 g + r][c] in element r, so the 4 rows a lane
+// owns in a 16-row output tile are exactly the 4 K values it needs when that
+// tile becomes the next product's K chunk: chained products never move data
+// between lanes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fno {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef short s4v __attribute__((ext_vector_type(4)));
+
+// Operand fragment type of the MFMA for activation/compute type T.
+template <typename T> struct OpOf;
+template <> struct OpOf<float> { typedef f4v type; };
+template <> struct OpOf<__bf16> { typedef s4v type; };
+
+__device__ __forceinline__ f4v mma16(f4v a, f4v b, f4v acc)
+{
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], acc, 0, 0, 0);
+    return acc;
+}
+
+__device__ __forceinline__ f4v mma16(s4v a, s4v b, f4v acc)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+}
+
+__device__ __forceinline__ short bf16_bits(float v) { return __builtin_bit_cast(short, (__bf16)v); }
+
+// Accumulator (4 floats) -> operand fragment of type T.
+template <typename T> __device__ __forceinline__ typename OpOf<T>::type to_op(f4v v);
+template <> __device__ __forceinline__ f4v to_op<float>(f4v v) { return v; }
+template <> __device__ __forceinline__ s4v to_op<__bf16>(f4v v)
+{
+    s4v r;
+    r[0] = bf16_bits(v[0]);
+    r[1] = bf16_bits(v[1]);
+    r[2] = bf16_bits(v[2]);
+    r[3] = bf16_bits(v[3]);
+    return r;
+}
+
+template <typename T> __device__ __forceinline__ typename OpOf<T>::type op_zero();
+template <> __device__ __forceinline__ f4v op_zero<float>() { return f4v{0.f, 0.f, 0.f, 0.f}; }
+template <> __device__ __forceinline__ s4v op_zero<__bf16>() { return s4v{0, 0, 0, 0}; }
+
+__device__ __forceinline__ f4v f4_zero() { return f4v{0.f, 0.f, 0.f, 0.f}; }
+
+// Value of lane (l & ~15) | ((l + 8) & 15): rotate each row of 16 lanes by 8 (DPP row_ror:8).
+__device__ __forceinline__ float row_ror8(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false));
+}
+
+// Element j of a fragment as float.
+__device__ __forceinline__ float op_get(f4v v, int j) { return v[j]; }
+__device__ __forceinline__ float op_get(s4v v, int j)
+{
+    return __uint_as_float(((unsigned)(unsigned short)v[j]) << 16);
+}
+
+}  // namespace fno

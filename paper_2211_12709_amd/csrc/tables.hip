@@ -1,0 +1,147 @@
+// tables.hip -- basis tables of the MFMA kernels, stored directly in MFMA
+// fragment order (see mfma_common.h): entry [tile...][lane][j] is the value a
+// lane feeds to the matrix core.  Every value is computed in FP64 on the GPU
+// (phase k*n reduced modulo N exactly in 64-bit integers), then rounded once
+// to float and, for the bfloat16 kernels, split into hi = bf16(v) and
+// lo = bf16(v - hi) so that hi + lo carries about 16 significant bits.
+//
+// Retained frequencies follow the truncation of Alg. 2 (Sec. IV-C): compact
+// index j < m is frequency j and j >= m is N - 2m + j on x, y, z; on t it is j.
+#include "fno_internal.h"
+#include "mfma_common.h"
+
+namespace fno {
+
+__device__ __forceinline__ double ang(long long k, long long n, long long N)
+{
+    return 6.283185307179586476925286766559 * (double)((k * n) % N) / (double)N;
+}
+
+__device__ __forceinline__ long long freq(int j, int m, int N) { return j < m ? j : (long long)N - 2 * m + j; }
+
+__device__ __forceinline__ double ct_weight(int kt, int Nt, double inv_ncell, int kind)
+{
+    if (kind == 0) return 1.0;
+    const double c = (kt == 0 || (Nt % 2 == 0 && 2 * kt == Nt)) ? 1.0 : 2.0;
+    return c * inv_ncell;
+}
+
+// kind: TAB_T_FWD / TAB_T_BWD (t-step B operand, weights 1 or c(kt)/N),
+//       TAB_Z_FWD (z-step A operand), TAB_Y_FWD (y-step A operand).
+enum { TAB_T_FWD = 0, TAB_T_BWD = 1, TAB_Z_FWD = 2, TAB_Y_FWD = 3 };
+
+struct TabGeom {
+    int Nt, Kt, NTT, NQ;
+    int Nz, Kz, mz, Kzp, NZB, MZ;
+    int Ny, Ky, my, Kyp, MY, Yc, QY, NYC;
+    double inv_ncell;
+};
+
+__global__ void k_gen_tab(int kind, TabGeom G, long long n, float *__restrict__ f32, short *__restrict__ hi,
+                          short *__restrict__ lo)
+{
+    long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int j = (int)(e & 3), lane = (int)((e >> 2) & 63);
+    const int g = lane >> 4, c = lane & 15;
+    long long tile = e >> 8;
+    double v = 0.0;
+    if (kind == TAB_T_FWD || kind == TAB_T_BWD) {
+        const int nt = (int)(tile % G.NTT), q = (int)(tile / G.NTT);
+        const int t = 16 * q + 4 * g + j;
+        const int ri = G.NTT == 1 ? c / 8 : nt;
+        const int kt = G.NTT == 1 ? c % 8 : c;
+        if (t < G.Nt && kt < G.Kt) {
+            const double th = ang(kt, t, G.Nt);
+            const double w = ct_weight(kt, G.Nt, G.inv_ncell, kind == TAB_T_BWD);
+            v = ri == 0 ? w * cos(th) : -w * sin(th);
+        }
+    } else if (kind == TAB_Z_FWD) {
+        const int mb = (int)(tile % G.MZ), zb = (int)(tile / G.MZ);
+        const int m = mb * 16 + c, z = zb * 16 + 4 * g + j;
+        const int h = m < G.Kzp ? 0 : 1, kz = m < G.Kzp ? m : m - G.Kzp;
+        if (z < G.Nz && kz < G.Kz) {
+            const double th = ang(freq(kz, G.mz, G.Nz), z, G.Nz);
+            v = h == 0 ? cos(th) : sin(th);
+        }
+    } else if (kind == TAB_Y_FWD) {
+        const int mb = (int)(tile % G.MY);
+        const long long r1 = tile / G.MY;
+        const int q = (int)(r1 % G.QY), ych = (int)(r1 / G.QY);
+        const int row = mb * 16 + c, ro = row / G.Kyp, ky = row % G.Kyp;
+        const int k = 16 * q + 4 * g + j, ri = k / G.Yc, y = ych * G.Yc + k % G.Yc;
+        if (ky < G.Ky && y < G.Ny) {
+            const double th = ang(freq(ky, G.my, G.Ny), y, G.Ny);
+            const double cs = cos(th), sn = sin(th);
+            // [[cos, sin], [-sin, cos]]: (Re, Im) out from (Re, Im) in for exp(-i theta)
+            v = ro == 0 ? (ri == 0 ? cs : sn) : (ri == 0 ? -sn : cs);
+        }
+    }
+    const float vf = (float)v;
+    f32[e] = vf;
+    if (hi) {
+        const __bf16 h = (__bf16)vf;
+        const float rem = (float)(v - (double)(float)h);
+        hi[e] = __builtin_bit_cast(short, h);
+        lo[e] = __builtin_bit_cast(short, (__bf16)rem);
+    }
+}
+
+void fill_geom(const Dims &d, int dtype, TabGeom &G)
+{
+    G.Nt = d.N[3];
+    G.Kt = d.K[3];
+    G.NTT = d.K[3] <= 8 ? 1 : 2;
+    G.NQ = (d.N[3] + 15) / 16;
+    G.Nz = d.N[2];
+    G.Kz = d.K[2];
+    G.mz = d.m[2];
+    G.Kzp = (d.K[2] + 15) / 16 * 16;
+    G.NZB = (d.N[2] + 15) / 16;
+    G.MZ = 2 * G.Kzp / 16;
+    G.Ny = d.N[1];
+    G.Ky = d.K[1];
+    G.my = d.m[1];
+    G.Kyp = (d.K[1] + 15) / 16 * 16;
+    G.MY = 2 * G.Kyp / 16;
+    G.Yc = dtype == FNO_BF16 ? 32 : 16;
+    G.QY = 2 * G.Yc / 16;
+    G.NYC = (d.N[1] + G.Yc - 1) / G.Yc;
+    G.inv_ncell = 1.0 / (double)d.ncell;
+}
+
+long long tab_values(int kind, const TabGeom &G)
+{
+    switch (kind) {
+    case TAB_T_FWD:
+    case TAB_T_BWD: return (long long)G.NQ * G.NTT * 256;
+    case TAB_Z_FWD: return (long long)G.NZB * G.MZ * 256;
+    case TAB_Y_FWD: return (long long)G.NYC * G.QY * G.MY * 256;
+    }
+    return 0;
+}
+
+void gen_tab(int kind, const TabGeom &G, float *f32, short *hi, short *lo, hipStream_t st)
+{
+    const long long n = tab_values(kind, G);
+    hipLaunchKernelGGL(k_gen_tab, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, kind, G, n, f32, hi, lo);
+}
+
+}  // namespace fno
+
+namespace fno {
+
+TabGeom *new_geom(const Dims &d, int dtype)
+{
+    TabGeom *g = new TabGeom();
+    fill_geom(d, dtype, *g);
+    return g;
+}
+
+void free_geom(TabGeom *g) { delete g; }
+
+long long tab_count(int kind, const TabGeom &G) { return tab_values(kind, G); }
+
+void gen_frag(int kind, const TabGeom &G, const Tables::Frag &f, hipStream_t st) { gen_tab(kind, G, f.f, f.hi, f.lo, st); }
+
+}  // namespace fno
