@@ -75,27 +75,43 @@ def flop_model(B, Ci, Co, grid, modes):
 
 
 def kernel_model(name, B, Ci, Co, grid, modes, act_bytes):
-    """Algorithmic HBM bytes and flops of one launch of a kernel, counting what
-    the kernel has to read and write across its boundary."""
+    """Algorithmic HBM bytes and model flops of ONE launch of a library kernel
+    in the block step: what the kernel must read and write across its own
+    boundary (activations, spectra, weights), and the flops of the truncated
+    separable transform stages it performs."""
     nx, ny, nz, nt = grid
     mx, my, mz, mt = modes
     N = nx * ny * nz * nt
-    C = Co  # block runs here have Ci == Co
-    A = B * C * N * act_bytes
-    kplane = B * C * nx * ny * (2 * mz) * mt * 8           # t,z spectrum (complex64)
+    C = Co  # the benchmark block has Ci == Co
+    A = B * C * N * act_bytes                                # one activation tensor
+    kx, ky, kz = 2 * mx, 2 * my, 2 * mz
+    t1 = B * C * nx * ny * kz * mt * 8                       # t,z spectrum, complex64
+    t2 = B * C * nx * ky * kz * mt * 8                       # t,z,y spectrum
+    sp = B * C * kx * ky * kz * mt * 8                       # retained spectrum
+    W = Ci * Co * kx * ky * kz * mt * 8
     t_fl = 4 * B * C * N * mt
-    z_fl = 8 * B * C * nx * ny * mt * nz * 2 * mz
+    z_fl = 8 * B * C * nx * ny * mt * nz * kz
+    y_fl = 8 * B * C * nx * kz * mt * ny * ky
+    x_fl = 8 * B * C * ky * kz * mt * nx * kx
     pw = 2 * B * Ci * Co * N
-    if name.startswith("fwd_tz"):
-        a = A if "bf16" in name else B * C * N * 4
-        return dict(bytes=a + kplane, flops=t_fl + z_fl, unit="plane", units=B * C * nx * ny)
-    if name == "inv_zt_block":
-        return dict(bytes=kplane + 2 * A, flops=t_fl + z_fl + pw, unit="plane", units=B * nx * ny)
-    if name == "bwd_gz":
-        return dict(bytes=kplane + 2 * A + B * Co * N * 4, flops=t_fl + z_fl + pw, unit="plane", units=B * nx * ny)
-    if name == "inv_zt_adj":
-        return dict(bytes=kplane + B * Co * N * 4 + A, flops=t_fl + z_fl + pw, unit="plane", units=B * nx * ny)
-    return None
+    models = {
+        "tzy_fwd<bf16>": (B * C * N * 2 + t2, t_fl + z_fl + y_fl),
+        "tzy_fwd<f32>": (B * C * N * 4 + t2, t_fl + z_fl + y_fl),
+        "zt_plain": (t1 + A, t_fl + z_fl),
+        "zt_block": (t1 + 2 * A, t_fl + z_fl + pw),
+        "zt_bwd": (t1 + 3 * A, t_fl + z_fl + 2 * pw),
+        "zt_adj": (t1 + 2 * A, t_fl + z_fl + pw),
+        "axis_fwd_x": (t2 + sp, x_fl),
+        "axis_inv_x": (sp + t2, x_fl),
+        "axis_inv_y": (t2 + t1, y_fl),
+        "axis_fwd_y": (t1 + t2, y_fl),
+        "mix_fwd": (2 * sp + W, 8 * B * Ci * Co * kx * ky * kz * mt),
+        "mix_bwd": (3 * sp + 2 * W, 16 * B * Ci * Co * kx * ky * kz * mt),
+    }
+    if name not in models:
+        return None
+    by, fl = models[name]
+    return dict(bytes=by, flops=fl)
 
 
 # ------------------------------------------------------------------ helpers

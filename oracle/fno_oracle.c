@@ -555,3 +555,149 @@ void oracle_block_bwd(const int *d, const double *x, const double *w, const doub
         }
     free(z);
 }
+
+/* ------------------------------------------------------------------------ */
+/* Network glue of Alg. 1: encoder (lifting), decoder (projection), loss.    */
+
+/* Lifting (Alg. 1, encoder): y[b][o][n] = GELU(sum_i we[o][i] x[b][i][n] + be[o]).
+ * we is [Co][Ci], be (nullable) [Co]; N is the number of grid points. */
+void oracle_lift_fwd(int B, int Ci, int Co, long N, const double *x, const double *we, const double *be, double *y)
+{
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (long b = 0; b < B; b++)
+        for (long o = 0; o < Co; o++)
+            for (long p = 0; p < N; p++) {
+                double acc = be ? be[o] : 0.0;
+                for (long i = 0; i < Ci; i++) acc += we[o * Ci + i] * x[((size_t)b * Ci + i) * N + p];
+                y[((size_t)b * Co + o) * N + p] = oracle_gelu(acc);
+            }
+}
+
+/* Backward of the lifting layer; gx, gwe, gbe nullable (written, not added). */
+void oracle_lift_bwd(int B, int Ci, int Co, long N, const double *x, const double *we, const double *be,
+                     const double *gy, double *gx, double *gwe, double *gbe)
+{
+    double *gz = (double *)malloc(sizeof(double) * (size_t)B * Co * N);
+    #pragma omp parallel for collapse(2) schedule(static)
+    for (long b = 0; b < B; b++)
+        for (long o = 0; o < Co; o++)
+            for (long p = 0; p < N; p++) {
+                double acc = be ? be[o] : 0.0;
+                for (long i = 0; i < Ci; i++) acc += we[o * Ci + i] * x[((size_t)b * Ci + i) * N + p];
+                gz[((size_t)b * Co + o) * N + p] = gy[((size_t)b * Co + o) * N + p] * oracle_gelu_grad(acc);
+            }
+    if (gx) {
+        #pragma omp parallel for collapse(2) schedule(static)
+        for (long b = 0; b < B; b++)
+            for (long i = 0; i < Ci; i++)
+                for (long p = 0; p < N; p++) {
+                    double acc = 0;
+                    for (long o = 0; o < Co; o++) acc += we[o * Ci + i] * gz[((size_t)b * Co + o) * N + p];
+                    gx[((size_t)b * Ci + i) * N + p] = acc;
+                }
+    }
+    if (gwe) {
+        #pragma omp parallel for collapse(2) schedule(static)
+        for (long o = 0; o < Co; o++)
+            for (long i = 0; i < Ci; i++) {
+                double acc = 0;
+                for (long b = 0; b < B; b++)
+                    for (long p = 0; p < N; p++) acc += gz[((size_t)b * Co + o) * N + p] * x[((size_t)b * Ci + i) * N + p];
+                gwe[o * Ci + i] = acc;
+            }
+    }
+    if (gbe) {
+        for (long o = 0; o < Co; o++) {
+            double acc = 0;
+            for (long b = 0; b < B; b++)
+                for (long p = 0; p < N; p++) acc += gz[((size_t)b * Co + o) * N + p];
+            gbe[o] = acc;
+        }
+    }
+    free(gz);
+}
+
+/* Projection (Alg. 1, decoder, two pointwise layers with GELU between them):
+ * h = GELU(w1 x + b1) with H hidden channels, y = w2 h + b2.
+ * w1 [H][Ci], b1 [H], w2 [Co][H], b2 [Co] (biases nullable). */
+void oracle_proj_fwd(int B, int Ci, int H, int Co, long N, const double *x, const double *w1, const double *b1,
+                     const double *w2, const double *b2, double *y)
+{
+    #pragma omp parallel
+    {
+        double *h = (double *)malloc(sizeof(double) * H);
+        #pragma omp for collapse(2) schedule(static)
+        for (long b = 0; b < B; b++)
+            for (long p = 0; p < N; p++) {
+                for (long k = 0; k < H; k++) {
+                    double acc = b1 ? b1[k] : 0.0;
+                    for (long i = 0; i < Ci; i++) acc += w1[k * Ci + i] * x[((size_t)b * Ci + i) * N + p];
+                    h[k] = oracle_gelu(acc);
+                }
+                for (long o = 0; o < Co; o++) {
+                    double acc = b2 ? b2[o] : 0.0;
+                    for (long k = 0; k < H; k++) acc += w2[o * H + k] * h[k];
+                    y[((size_t)b * Co + o) * N + p] = acc;
+                }
+            }
+        free(h);
+    }
+}
+
+/* Backward of the projection; every output nullable, written (not added). */
+void oracle_proj_bwd(int B, int Ci, int H, int Co, long N, const double *x, const double *w1, const double *b1,
+                     const double *w2, const double *b2, const double *gy, double *gx, double *gw1, double *gb1,
+                     double *gw2, double *gb2)
+{
+    (void)b2;
+    if (gw1) memset(gw1, 0, sizeof(double) * H * Ci);
+    if (gb1) memset(gb1, 0, sizeof(double) * H);
+    if (gw2) memset(gw2, 0, sizeof(double) * Co * H);
+    if (gb2) memset(gb2, 0, sizeof(double) * Co);
+    double *z = (double *)malloc(sizeof(double) * H), *gh = (double *)malloc(sizeof(double) * H);
+    /* one pass over points in a fixed order keeps the weight-gradient sums deterministic */
+    for (long b = 0; b < B; b++)
+        for (long p = 0; p < N; p++) {
+            for (long k = 0; k < H; k++) {
+                double acc = b1 ? b1[k] : 0.0;
+                for (long i = 0; i < Ci; i++) acc += w1[k * Ci + i] * x[((size_t)b * Ci + i) * N + p];
+                z[k] = acc;
+            }
+            for (long k = 0; k < H; k++) {
+                double g = 0;
+                for (long o = 0; o < Co; o++) g += w2[o * H + k] * gy[((size_t)b * Co + o) * N + p];
+                gh[k] = g * oracle_gelu_grad(z[k]);
+            }
+            for (long o = 0; o < Co; o++) {
+                const double g = gy[((size_t)b * Co + o) * N + p];
+                if (gb2) gb2[o] += g;
+                if (gw2)
+                    for (long k = 0; k < H; k++) gw2[o * H + k] += g * oracle_gelu(z[k]);
+            }
+            for (long k = 0; k < H; k++) {
+                if (gb1) gb1[k] += gh[k];
+                if (gw1)
+                    for (long i = 0; i < Ci; i++) gw1[k * Ci + i] += gh[k] * x[((size_t)b * Ci + i) * N + p];
+            }
+            if (gx)
+                for (long i = 0; i < Ci; i++) {
+                    double acc = 0;
+                    for (long k = 0; k < H; k++) acc += w1[k * Ci + i] * gh[k];
+                    gx[((size_t)b * Ci + i) * N + p] = acc;
+                }
+        }
+    free(z);
+    free(gh);
+}
+
+/* Mean-squared-error loss L = (1/n) sum (y - t)^2 and its gradient gy = 2 (y - t)/n (nullable). */
+double oracle_mse(long n, const double *y, const double *t, double *gy)
+{
+    double acc = 0;
+    for (long i = 0; i < n; i++) {
+        const double d = y[i] - t[i];
+        acc += d * d;
+        if (gy) gy[i] = 2.0 * d / (double)n;
+    }
+    return acc / (double)n;
+}

@@ -63,6 +63,17 @@ def load(path: str):
     L.oracle_spectral_bwd.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
     L.oracle_block_fwd.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp]
     L.oracle_block_bwd.argtypes = [_ip, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.oracle_lift_fwd.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_long, _dp, _dp, _dp, _dp]
+    L.oracle_lift_bwd.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_long, _dp, _dp, _dp, _dp, _dp,
+                                  _dp, _dp]
+    L.oracle_proj_fwd.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_long, _dp, _dp,
+                                  _dp, _dp, _dp, _dp]
+    L.oracle_proj_bwd.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_long, _dp, _dp,
+                                  _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.oracle_mse.argtypes = [ctypes.c_long, _dp, _dp, _dp]
+    L.oracle_mse.restype = ctypes.c_double
+    for f in ("oracle_lift_fwd", "oracle_lift_bwd", "oracle_proj_fwd", "oracle_proj_bwd"):
+        getattr(L, f).restype = None
     for f in ("oracle_dft_fwd", "oracle_synth", "oracle_dft_fwd_direct", "oracle_dft_fwd_modes",
               "oracle_synth_points", "oracle_mix", "oracle_mix_bwd", "oracle_spectral_fwd",
               "oracle_spectral_bwd", "oracle_block_fwd", "oracle_block_bwd"):
@@ -234,6 +245,90 @@ def block_bwd(d: Dims, x, w, wpw, bpw, gy):
     return gx, gw, gwpw, gb
 
 
-__all__ = ["Dims", "build_oracle", "check_dims", "ct", "gelu", "gelu_grad", "inverse_weights",
+# ------------------------------------------------------------------ network glue (Alg. 1)
+def lift_fwd(x, we, be):
+    """Encoder: GELU(we x + be) pointwise; x [B, Ci, *grid] -> [B, Co, *grid]."""
+    x = _f64(x)
+    B, Ci = x.shape[:2]
+    Co = we.shape[0]
+    N = int(np.prod(x.shape[2:]))
+    y = np.zeros((B, Co, *x.shape[2:]))
+    lib().oracle_lift_fwd(B, Ci, Co, N, _p(x), _p(_f64(we)), _p(_f64(be) if be is not None else None), _p(y))
+    return y
+
+
+def lift_bwd(x, we, be, gy, need_gx=False):
+    x = _f64(x)
+    B, Ci = x.shape[:2]
+    Co = we.shape[0]
+    N = int(np.prod(x.shape[2:]))
+    gx = np.zeros_like(x) if need_gx else None
+    gwe = np.zeros((Co, Ci))
+    gbe = np.zeros(Co)
+    lib().oracle_lift_bwd(B, Ci, Co, N, _p(x), _p(_f64(we)), _p(_f64(be) if be is not None else None),
+                          _p(_f64(gy)), _p(gx), _p(gwe), _p(gbe))
+    return gx, gwe, gbe
+
+
+def proj_fwd(x, w1, b1, w2, b2):
+    """Decoder: w2 GELU(w1 x + b1) + b2 pointwise."""
+    x = _f64(x)
+    B, Ci = x.shape[:2]
+    H, Co = w1.shape[0], w2.shape[0]
+    N = int(np.prod(x.shape[2:]))
+    y = np.zeros((B, Co, *x.shape[2:]))
+    lib().oracle_proj_fwd(B, Ci, H, Co, N, _p(x), _p(_f64(w1)), _p(_f64(b1)), _p(_f64(w2)), _p(_f64(b2)), _p(y))
+    return y
+
+
+def proj_bwd(x, w1, b1, w2, b2, gy):
+    x = _f64(x)
+    B, Ci = x.shape[:2]
+    H, Co = w1.shape[0], w2.shape[0]
+    N = int(np.prod(x.shape[2:]))
+    gx = np.zeros_like(x)
+    gw1, gb1 = np.zeros((H, Ci)), np.zeros(H)
+    gw2, gb2 = np.zeros((Co, H)), np.zeros(Co)
+    lib().oracle_proj_bwd(B, Ci, H, Co, N, _p(x), _p(_f64(w1)), _p(_f64(b1)), _p(_f64(w2)), _p(_f64(b2)),
+                          _p(_f64(gy)), _p(gx), _p(gw1), _p(gb1), _p(gw2), _p(gb2))
+    return gx, gw1, gb1, gw2, gb2
+
+
+def mse(y, t):
+    """(loss, gradient) of the mean-squared error."""
+    y = _f64(y)
+    g = np.zeros_like(y)
+    L = lib().oracle_mse(y.size, _p(y), _p(_f64(t)), _p(g))
+    return L, g
+
+
+def fno_fwd(d: Dims, x, params):
+    """Alg. 1 on one device: lift -> blocks -> projection.  params holds
+    'lift': (we, be), 'blocks': [(w, wpw, bpw), ...], 'proj': (w1, b1, w2, b2).
+    Returns the output and the list of block inputs (for the backward)."""
+    h = lift_fwd(x, *params["lift"])
+    acts = [h]
+    for (w, wpw, bpw) in params["blocks"]:
+        h = block_fwd(d, h, w, wpw, bpw)
+        acts.append(h)
+    y = proj_fwd(h, *params["proj"])
+    return y, acts
+
+
+def fno_bwd(d: Dims, x, params, acts, gy):
+    """Gradients of every parameter for the upstream gradient gy (same structure as params)."""
+    g, gw1, gb1, gw2, gb2 = proj_bwd(acts[-1], *params["proj"], gy)
+    grads_blocks = []
+    for bi in range(len(params["blocks"]) - 1, -1, -1):
+        w, wpw, bpw = params["blocks"][bi]
+        g, gw, gwpw, gb = block_bwd(d, acts[bi], w, wpw, bpw, g)
+        grads_blocks.append((gw, gwpw, gb))
+    grads_blocks.reverse()
+    _, gwe, gbe = lift_bwd(x, *params["lift"], g)
+    return {"lift": (gwe, gbe), "blocks": grads_blocks, "proj": (gw1, gb1, gw2, gb2)}
+
+
+__all__ = ["lift_fwd", "lift_bwd", "proj_fwd", "proj_bwd", "mse", "fno_fwd", "fno_bwd",
+           "Dims", "build_oracle", "check_dims", "ct", "gelu", "gelu_grad", "inverse_weights",
            "dft_fwd", "synth", "synth_points", "dft_modes", "mix", "mix_bwd", "spectral_fwd",
            "spectral_bwd", "block_fwd", "block_bwd"]

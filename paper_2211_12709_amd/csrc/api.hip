@@ -43,6 +43,22 @@ struct TzyTabs {
     const void *t, *t_lo, *z, *z_lo, *y, *y_lo;
 };
 bool tzy_supported(const Dims &d, int dtype);
+struct ZtTabs {
+    const void *z, *z_lo, *t, *t_lo;
+};
+enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3 };
+bool zt_supported(const Dims &d, int dtype);
+int zt_grid(const Dims &d);
+template <typename T>
+hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const float2 *u, T *out, const T *src, const T *gy,
+                     const float *wpw, const float *bpw, float *part, const ZtTabs &tb, int accumulate, hipStream_t st);
+template <typename TC>
+hipError_t launch_axis_mfma(const float2 *in, float2 *out, const void *tab, const void *tab_lo, long long outer,
+                            int Nin, int Nout, long long cols, hipStream_t st);
+size_t axis_lds_bytes(int Ninp, int elem);
+TabGeom *new_axis_geom(const Dims &d, int a, bool forward);
+void launch_pw_reduce(const float *part, float *gwpw, float *gb, int Ci, int Co, int nchunk, int accumulate,
+                      hipStream_t st);
 template <typename T>
 hipError_t launch_tzy(const T *x, float2 *t2, long long slabs, const TzyTabs &tb, const Dims &d, hipStream_t st);
 size_t inv_zt_lds(const Dims &d);
@@ -156,7 +172,8 @@ static WsPlan ws_plan(const Dims &d, int op)
     w.sp3 = take(sizeof(float2) * (size_t)(d.B * C * d.nmode));
     if (op == FNO_OP_BLOCK_BWD) {
         w.gz = take(sizeof(float) * (size_t)(d.B * d.Co * d.ncell));
-        w.part = take(sizeof(float) * (size_t)pw_wgrad_chunks(d.B * d.ncell) * d.Co * (d.Ci + 1));
+        const size_t chunks = std::max<size_t>(pw_wgrad_chunks(d.B * d.ncell), (size_t)zt_grid(d) * 4);
+        w.part = take(sizeof(float) * chunks * d.Co * (d.Ci + 1));
     }
     w.total = off;
     return w;
@@ -185,6 +202,21 @@ static int finish()
 }
 
 // X^ of activations `in` (C channels) into xh, using t1/t2 as scratch.
+// One-axis contraction of complex spectra along axis ax (0 = x, 1 = y) on the
+// matrix cores (float operands): in [outer][Nin][cols] -> out [outer][Nout][cols].
+static void axis_stage(const fno_plan_t *p, int ax, bool forward, const float2 *in, float2 *out, long long outer,
+                       long long cols, hipStream_t st, const char *name)
+{
+    const Dims &d = p->d;
+    const int Nin = forward ? d.N[ax] : d.K[ax], Nout = forward ? d.K[ax] : d.N[ax];
+    const Tables::Frag &tb = forward ? p->tab.ax_fwd[ax] : p->tab.ax_inv[ax];
+    if (axis_lds_bytes((Nin + 15) / 16 * 16, 4) <= 160 * 1024) {
+        FNO_TIMED(p, st, name, (void)launch_axis_mfma<float>(in, out, tb.f, nullptr, outer, Nin, Nout, cols, st));
+    } else {
+        FNO_TIMED(p, st, name, launch_axis(in, out, p->tab.cs[ax], outer, Nin, Nout, cols, d.N[ax], forward ? 0 : 1, st));
+    }
+}
+
 template <typename T>
 static TzyTabs tzy_tabs(const fno_plan_t *p, const float *wt)
 {
@@ -212,12 +244,18 @@ static void forward_spectrum(const fno_plan_t *p, const T *in, int C, const floa
     } else {
         FNO_TIMED(p, st, sizeof(T) == 2 ? "fwd_tz<bf16>" : "fwd_tz<f32>",
                   launch_fwd_tz<T>(in, t1, (long long)d.B * C * d.N[0] * d.N[1], d, p->tab, wt, st));
-        FNO_TIMED(p, st, "axis_fwd_y",
-                  launch_axis(t1, t2, p->tab.cs[1], (long long)d.B * C * d.N[0], d.N[1], d.K[1], d.kplane, d.N[1], 0,
-                              st));
+        axis_stage(p, 1, true, t1, t2, (long long)d.B * C * d.N[0], d.kplane, st, "axis_fwd_y");
     }
-    FNO_TIMED(p, st, "axis_fwd_x",
-              launch_axis(t2, xh, p->tab.cs[0], (long long)d.B * C, d.N[0], d.K[0], d.P, d.N[0], 0, st));
+    axis_stage(p, 0, true, t2, xh, (long long)d.B * C, d.P, st, "axis_fwd_x");
+}
+
+template <typename T>
+static ZtTabs zt_tabs(const fno_plan_t *p, bool adjoint)
+{
+    const Tables &tb = p->tab;
+    const Tables::Frag &tt = adjoint ? tb.t_syn_adj : tb.t_syn_inv;
+    if (sizeof(T) == 2) return ZtTabs{tb.z_syn.hi, tb.z_syn.lo, tt.hi, tt.lo};
+    return ZtTabs{tb.z_syn.f, nullptr, tt.f, nullptr};
 }
 
 // Inverse x then y stage of a retained spectrum (C channels): spec -> u2 -> u1.
@@ -225,11 +263,8 @@ static void inverse_xy(const fno_plan_t *p, const float2 *spec, int C, float2 *u
                        bool skip_x = false)
 {
     const Dims &d = p->d;
-    if (!skip_x)
-        FNO_TIMED(p, st, "axis_inv_x",
-                  launch_axis(spec, u2, p->tab.cs[0], (long long)d.B * C, d.K[0], d.N[0], d.P, d.N[0], 1, st));
-    FNO_TIMED(p, st, "axis_inv_y",
-              launch_axis(u2, u1, p->tab.cs[1], (long long)d.B * C * d.N[0], d.K[1], d.N[1], d.kplane, d.N[1], 1, st));
+    if (!skip_x) axis_stage(p, 0, false, spec, u2, (long long)d.B * C, d.P, st, "axis_inv_x");
+    axis_stage(p, 1, false, u2, u1, (long long)d.B * C * d.N[0], d.kplane, st, "axis_inv_y");
 }
 
 template <typename T>
@@ -254,9 +289,16 @@ static int spectral_or_block_fwd(const fno_plan_t *p, const void *x_, const void
     forward_spectrum<T>(p, x, d.Ci, p->tab.wt_one, t1, t2, xh, st);
     FNO_TIMED(p, st, "mix_fwd", launch_mix_fwd(xh, (const float2 *)w_, yh, d.B, d.Ci, d.Co, d.nmode, st));
     inverse_xy(p, yh, d.Co, u2, t1, st);
-    FNO_TIMED(p, st, block ? "inv_zt_block" : "inv_zt_plain",
-              launch_inv_zt<T>(block ? EPI_BLOCK : EPI_PLAIN, t1, (T *)y_, d.Co, d, p->tab, p->tab.wt_inv, x,
-                               (const float *)wpw, (const float *)bpw, nullptr, d.Ci, 0, st));
+    if (zt_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
+        FNO_TIMED(p, st, block ? "zt_block" : "zt_plain",
+                  (void)launch_zt<T>(block ? ZEPI_BLOCK : ZEPI_PLAIN, d, d.Co, block ? d.Ci : 0, t1, (T *)y_, x,
+                                     nullptr, (const float *)wpw, (const float *)bpw, nullptr, zt_tabs<T>(p, false), 0,
+                                     st));
+    } else {
+        FNO_TIMED(p, st, block ? "inv_zt_block" : "inv_zt_plain",
+                  launch_inv_zt<T>(block ? EPI_BLOCK : EPI_PLAIN, t1, (T *)y_, d.Co, d, p->tab, p->tab.wt_inv, x,
+                                   (const float *)wpw, (const float *)bpw, nullptr, d.Ci, 0, st));
+    }
     return finish();
 }
 
@@ -293,9 +335,15 @@ static int spectral_bwd_impl(const fno_plan_t *p, const void *x_, const void *ca
                              d.nmode, accumulate, st));
     if (gx_) {
         inverse_xy(p, gxh, d.Ci, t2, t1, st);
-        FNO_TIMED(p, st, "inv_zt_adj",
-                  launch_inv_zt<T>(EPI_ADJ, t1, (T *)gx_, d.Ci, d, p->tab, p->tab.wt_one, nullptr, nullptr, nullptr,
-                                   nullptr, d.Co, accumulate, st));
+        if (zt_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
+            FNO_TIMED(p, st, "zt_adj",
+                      (void)launch_zt<T>(ZEPI_ADJ, d, d.Ci, 0, t1, (T *)gx_, nullptr, nullptr, nullptr, nullptr,
+                                         nullptr, zt_tabs<T>(p, true), accumulate, st));
+        } else {
+            FNO_TIMED(p, st, "inv_zt_adj",
+                      launch_inv_zt<T>(EPI_ADJ, t1, (T *)gx_, d.Ci, d, p->tab, p->tab.wt_one, nullptr, nullptr,
+                                       nullptr, nullptr, d.Co, accumulate, st));
+        }
     }
     return finish();
 }
@@ -324,6 +372,24 @@ static int block_bwd_impl(const fno_plan_t *p, const void *x_, const void *cache
     const float *wpw = (const float *)wpw_, *bpw = (const float *)bpw_;
     // recompute the pre-activation from the cached x-inverse of Y^, then gz
     inverse_xy(p, nullptr, d.Co, const_cast<float2 *>(u2), t1, st, true);
+    if (zt_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
+        T *gzt = (T *)gz;  // gz stored in the activation type
+        FNO_TIMED(p, st, "zt_bwd",
+                  (void)launch_zt<T>(ZEPI_BWD, d, d.Co, d.Ci, t1, gzt, x, (const T *)gy_, wpw, bpw, part,
+                                     zt_tabs<T>(p, false), 0, st));
+        if (gwpw_ || gb_)
+            FNO_TIMED(p, st, "pw_reduce",
+                      launch_pw_reduce(part, (float *)gwpw_, (float *)gb_, d.Ci, d.Co, zt_grid(d) * 4, accumulate, st));
+        forward_spectrum<T>(p, gzt, d.Co, p->tab.wt_inv, t1, t2, gyh, st);
+        FNO_TIMED(p, st, "mix_bwd",
+                  launch_mix_bwd(xh, (const float2 *)w_, gyh, gxh, (float2 *)gw_, d.B, d.Ci, d.Co, d.nmode, accumulate,
+                                 st));
+        inverse_xy(p, gxh, d.Ci, t2, t1, st);
+        FNO_TIMED(p, st, "zt_adj",
+                  (void)launch_zt<T>(ZEPI_ADJ, d, d.Ci, d.Co, t1, (T *)gx_, gzt, nullptr, wpw, nullptr, nullptr,
+                                     zt_tabs<T>(p, true), accumulate, st));
+        return finish();
+    }
     FNO_TIMED(p, st, "bwd_gz", launch_bwd_gz<T>(t1, x, (const T *)gy_, gz, d, p->tab, wpw, bpw, st));
     if (gwpw_ || gb_)
         FNO_TIMED(p, st, "pw_wgrad",
@@ -369,6 +435,14 @@ int fno_plan_create(fno_plan_t **out, const fno_desc_t *desc)
     TabGeom *G32 = new_geom(d, FNO_F32), *G16 = new_geom(d, FNO_BF16);
     const long long n_t = tab_count(0, *G32), n_z = tab_count(2, *G32);
     const long long n_y32 = tab_count(3, *G32), n_y16 = tab_count(3, *G16);
+    const long long n_zs = tab_count(4, *G32), n_ts = tab_count(5, *G32);
+    TabGeom *GA[2][2];
+    long long n_ax[2][2];
+    for (int ax = 0; ax < 2; ax++)
+        for (int f = 0; f < 2; f++) {
+            GA[ax][f] = new_axis_geom(d, ax, f == 0);
+            n_ax[ax][f] = tab_count(f == 0 ? 7 : 8, *GA[ax][f]);
+        }
     size_t off = 0;
     size_t o_cs[4];
     for (int a = 0; a < 4; a++) { o_cs[a] = off; off += align_up(sizeof(float2) * (size_t)d.K[a] * d.N[a]); }
@@ -380,10 +454,18 @@ int fno_plan_create(fno_plan_t **out, const fno_desc_t *desc)
     const size_t o_zf = off; off += frag_bytes(n_z);
     const size_t o_y32 = off; off += frag_bytes(n_y32);
     const size_t o_y16 = off; off += frag_bytes(n_y16);
+    const size_t o_zs = off; off += frag_bytes(n_zs);
+    const size_t o_tsi = off; off += frag_bytes(n_ts);
+    const size_t o_tsa = off; off += frag_bytes(n_ts);
+    size_t o_ax[2][2];
+    for (int ax = 0; ax < 2; ax++)
+        for (int f = 0; f < 2; f++) { o_ax[ax][f] = off; off += frag_bytes(n_ax[ax][f]); }
     if (hipMalloc(&p->table_mem, off) != hipSuccess) {
         (void)hipGetLastError();
         free_geom(G32);
         free_geom(G16);
+        for (int ax = 0; ax < 2; ax++)
+            for (int f = 0; f < 2; f++) free_geom(GA[ax][f]);
         delete p;
         return FNO_ERR_OOM;
     }
@@ -403,6 +485,13 @@ int fno_plan_create(fno_plan_t **out, const fno_desc_t *desc)
     p->tab.z_fwd = frag_at(o_zf, n_z);
     p->tab.y_fwd_f32 = frag_at(o_y32, n_y32);
     p->tab.y_fwd_bf16 = frag_at(o_y16, n_y16);
+    p->tab.z_syn = frag_at(o_zs, n_zs);
+    p->tab.t_syn_inv = frag_at(o_tsi, n_ts);
+    p->tab.t_syn_adj = frag_at(o_tsa, n_ts);
+    for (int ax = 0; ax < 2; ax++) {
+        p->tab.ax_fwd[ax] = frag_at(o_ax[ax][0], n_ax[ax][0]);
+        p->tab.ax_inv[ax] = frag_at(o_ax[ax][1], n_ax[ax][1]);
+    }
     hipError_t ge = generate_tables(d, p->tab, nullptr);
     if (ge == hipSuccess) {
         gen_frag(0, *G32, p->tab.t_fwd, nullptr);
@@ -410,10 +499,19 @@ int fno_plan_create(fno_plan_t **out, const fno_desc_t *desc)
         gen_frag(2, *G32, p->tab.z_fwd, nullptr);
         gen_frag(3, *G32, p->tab.y_fwd_f32, nullptr);
         gen_frag(3, *G16, p->tab.y_fwd_bf16, nullptr);
+        gen_frag(4, *G32, p->tab.z_syn, nullptr);
+        gen_frag(5, *G32, p->tab.t_syn_inv, nullptr);
+        gen_frag(6, *G32, p->tab.t_syn_adj, nullptr);
+        for (int ax = 0; ax < 2; ax++) {
+            gen_frag(7, *GA[ax][0], p->tab.ax_fwd[ax], nullptr);
+            gen_frag(8, *GA[ax][1], p->tab.ax_inv[ax], nullptr);
+        }
         ge = hipGetLastError();
     }
     free_geom(G32);
     free_geom(G16);
+    for (int ax = 0; ax < 2; ax++)
+        for (int f = 0; f < 2; f++) free_geom(GA[ax][f]);
     if (ge != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         (void)hipFree(p->table_mem);
         delete p;

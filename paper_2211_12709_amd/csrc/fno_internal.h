@@ -31,6 +31,8 @@ struct Tables {
         short *hi, *lo;
     };
     Frag t_fwd, t_bwd, z_fwd, y_fwd_f32, y_fwd_bf16;
+    Frag z_syn, t_syn_inv, t_syn_adj;  // z and t synthesis (inverse / adjoint weights)
+    Frag ax_fwd[2], ax_inv[2];           // one-axis contractions along x (0) and y (1)
 };
 
 struct Dims {

@@ -75,8 +75,7 @@ __global__ void __launch_bounds__(256) k_tzy_fwd(const T *__restrict__ x, float2
     const int NT2 = (ncol + 15) / 16;
     const int per_wave = a.Yc / 4;  // planes per wave per chunk
 
-    // fragments of one plane: xa[zb][q] = x[y][zb*16 + c][16 q + 4 g .. + 3]
-    Op xa[NZBM][2];
+    // fragments of one plane: dst[zb][q] = x[y][zb*16 + c][16 q + 4 g .. + 3]
     auto load_plane = [&](int y, Op (&dst)[NZBM][2]) {
 #pragma unroll
         for (int zb = 0; zb < NZBM; zb++)
@@ -93,12 +92,12 @@ __global__ void __launch_bounds__(256) k_tzy_fwd(const T *__restrict__ x, float2
 
     const int nplanes = a.NYC * per_wave;  // plane slots of this wave
     auto plane_y = [&](int s) { return (s / per_wave) * a.Yc + (s % per_wave) * 4 + w; };
-    load_plane(plane_y(0), xa);
-    for (int s = 0; s < nplanes; s++) {
+    // one plane's t and z steps, staged into LDS (or zeros for a padding plane)
+    auto do_plane = [&](int s, const Op (&xa)[NZBM][2]) {
         const int yl = (s % per_wave) * 4 + w;
         const int y = plane_y(s);
-        Op xn[NZBM][2];
-        if (s + 1 < nplanes) load_plane(plane_y(s + 1), xn);
+        // keep the LDS basis reads inside the plane loop (no hoisting into registers)
+        asm volatile("" ::: "memory");
         if (y < Ny) {
             // Pc: cos rows (kz block kb), Ps: sin rows, both [kb][nt]
             f4v Pc[MAXKB][NTT], Ps[MAXKB][NTT];
@@ -171,11 +170,9 @@ __global__ void __launch_bounds__(256) k_tzy_fwd(const T *__restrict__ x, float2
                 tl[col * ldk + a.Yc + yl] = from_f32<T>(0.f);
             }
         }
-#pragma unroll
-        for (int zb = 0; zb < NZBM; zb++)
-#pragma unroll
-            for (int q = 0; q < 2; q++) xa[zb][q] = xn[zb][q];
-
+    };
+    // end of a chunk of Yc planes: the y step on the staged T1
+    auto chunk_end = [&](int s) {
         if ((s + 1) % per_wave == 0) {
             // chunk complete: y step over its 2*Yc K values
             const int ych = s / per_wave;
@@ -196,6 +193,17 @@ __global__ void __launch_bounds__(256) k_tzy_fwd(const T *__restrict__ x, float2
             }
             __syncthreads();
         }
+    };
+
+    Op xa[NZBM][2], xb[NZBM][2];
+    load_plane(plane_y(0), xa);
+    for (int s = 0; s < nplanes; s += 2) {  // nplanes is even: ping-pong without register copies
+        load_plane(plane_y(s + 1), xb);
+        do_plane(s, xa);
+        chunk_end(s);
+        if (s + 2 < nplanes) load_plane(plane_y(s + 2), xa);
+        do_plane(s + 1, xb);
+        chunk_end(s + 1);
     }
 
     // write T2[slab][ky][(kz, kt)] as (re, im): tile i (even) holds re rows, tile i + 1 the matching im rows

@@ -206,6 +206,13 @@ void launch_pw_wgrad(const float *gz, const T *x, float *part, float *gwpw, floa
                        nchunk, accumulate);
 }
 
+void launch_pw_reduce(const float *part, float *gwpw, float *gb, int Ci, int Co, int nchunk, int accumulate,
+                      hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pw_wgrad_reduce, dim3((Co * (Ci + 1) + 255) / 256), dim3(256), 0, st, part, gwpw, gb, Ci, Co,
+                       nchunk, accumulate);
+}
+
 template void launch_pw_wgrad<float>(const float *, const float *, float *, float *, float *, int, int, int, long long,
                                      int, hipStream_t);
 template void launch_pw_wgrad<__bf16>(const float *, const __bf16 *, float *, float *, float *, int, int, int,

@@ -28,13 +28,21 @@ __device__ __forceinline__ double ct_weight(int kt, int Nt, double inv_ncell, in
 
 // kind: TAB_T_FWD / TAB_T_BWD (t-step B operand, weights 1 or c(kt)/N),
 //       TAB_Z_FWD (z-step A operand), TAB_Y_FWD (y-step A operand).
-enum { TAB_T_FWD = 0, TAB_T_BWD = 1, TAB_Z_FWD = 2, TAB_Y_FWD = 3 };
+//       TAB_ZI (z-synthesis B operand), TAB_TI_INV / TAB_TI_ADJ (t-synthesis A
+//       operand with weights c(kt)/N or 1).
+//       TAB_AXF / TAB_AXI (one-axis contraction A operand, forward / inverse,
+//       for the axis described by the ax* fields).
+enum {
+    TAB_T_FWD = 0, TAB_T_BWD = 1, TAB_Z_FWD = 2, TAB_Y_FWD = 3, TAB_ZI = 4, TAB_TI_INV = 5, TAB_TI_ADJ = 6,
+    TAB_AXF = 7, TAB_AXI = 8
+};
 
 struct TabGeom {
     int Nt, Kt, NTT, NQ;
     int Nz, Kz, mz, Kzp, NZB, MZ;
     int Ny, Ky, my, Kyp, MY, Yc, QY, NYC;
     double inv_ncell;
+    int axN, axm, axNin, axNout, axNinp, axNoutp;  // one-axis contraction
 };
 
 __global__ void k_gen_tab(int kind, TabGeom G, long long n, float *__restrict__ f32, short *__restrict__ hi,
@@ -74,6 +82,38 @@ __global__ void k_gen_tab(int kind, TabGeom G, long long n, float *__restrict__ 
             const double th = ang(freq(ky, G.my, G.Ny), y, G.Ny);
             const double cs = cos(th), sn = sin(th);
             // [[cos, sin], [-sin, cos]]: (Re, Im) out from (Re, Im) in for exp(-i theta)
+            v = ro == 0 ? (ri == 0 ? cs : sn) : (ri == 0 ? -sn : cs);
+        }
+    } else if (kind == TAB_ZI) {
+        // B[(ri, kz)][z] for z tile zt and K chunk q: cos (ri = 0) / sin (ri = 1) of theta(kz, z)
+        const int q = (int)(tile % (2 * G.Kzp / 16)), zt = (int)(tile / (2 * G.Kzp / 16));
+        const int k = 16 * q + 4 * g + j, ri = k / G.Kzp, kz = k % G.Kzp, z = zt * 16 + c;
+        if (z < G.Nz && kz < G.Kz) {
+            const double th = ang(freq(kz, G.mz, G.Nz), z, G.Nz);
+            v = ri == 0 ? cos(th) : sin(th);
+        }
+    } else if (kind == TAB_TI_INV || kind == TAB_TI_ADJ) {
+        // A[t][(ri, kt)] for t tile mt and K chunk q: w cos (ri = 0) / -w sin (ri = 1) of 2 pi kt t / Nt
+        const int q = (int)(tile % G.NTT), mt = (int)(tile / G.NTT);
+        const int t = mt * 16 + c, k = 16 * q + 4 * g + j;
+        const int ri = G.NTT == 1 ? k / 8 : q;
+        const int kt = G.NTT == 1 ? k % 8 : k - 16 * q;
+        if (t < G.Nt && kt < G.Kt) {
+            const double th = ang(kt, t, G.Nt);
+            const double w = ct_weight(kt, G.Nt, G.inv_ncell, kind == TAB_TI_INV);
+            v = ri == 0 ? w * cos(th) : -w * sin(th);
+        }
+    } else if (kind == TAB_AXF || kind == TAB_AXI) {
+        const int QK = 2 * G.axNinp / 16;
+        const int q = (int)(tile % QK), mt = (int)(tile / QK);
+        const int row = mt * 16 + c, ro = row / G.axNoutp, jj = row % G.axNoutp;
+        const int k = 16 * q + 4 * g + j, ri = k / G.axNinp, nn = k % G.axNinp;
+        if (jj < G.axNout && nn < G.axNin) {
+            const bool fwd = kind == TAB_AXF;
+            // forward: jj retained frequency, nn grid point; inverse: jj grid point, nn retained frequency
+            const double th = fwd ? ang(freq(jj, G.axm, G.axN), nn, G.axN) : ang(freq(nn, G.axm, G.axN), jj, G.axN);
+            const double cs = cos(th), sn = fwd ? sin(th) : -sin(th);
+            // [[cos, s], [-s, cos]] with s = sin (exp(-i theta)) or -sin (exp(+i theta))
             v = ro == 0 ? (ri == 0 ? cs : sn) : (ri == 0 ? -sn : cs);
         }
     }
@@ -117,6 +157,11 @@ long long tab_values(int kind, const TabGeom &G)
     case TAB_T_BWD: return (long long)G.NQ * G.NTT * 256;
     case TAB_Z_FWD: return (long long)G.NZB * G.MZ * 256;
     case TAB_Y_FWD: return (long long)G.NYC * G.QY * G.MY * 256;
+    case TAB_ZI: return (long long)G.NZB * (2 * G.Kzp / 16) * 256;
+    case TAB_TI_INV:
+    case TAB_TI_ADJ: return (long long)((G.Nt + 15) / 16) * G.NTT * 256;
+    case TAB_AXF:
+    case TAB_AXI: return (long long)(2 * G.axNoutp / 16) * (2 * G.axNinp / 16) * 256;
     }
     return 0;
 }
@@ -135,6 +180,21 @@ TabGeom *new_geom(const Dims &d, int dtype)
 {
     TabGeom *g = new TabGeom();
     fill_geom(d, dtype, *g);
+    return g;
+}
+
+// Geometry of the one-axis contraction along axis a (0 = x, 1 = y), forward
+// (grid -> retained) or inverse (retained -> grid).
+TabGeom *new_axis_geom(const Dims &d, int a, bool forward)
+{
+    TabGeom *g = new TabGeom();
+    fill_geom(d, FNO_F32, *g);
+    g->axN = d.N[a];
+    g->axm = d.m[a];
+    g->axNin = forward ? d.N[a] : d.K[a];
+    g->axNout = forward ? d.K[a] : d.N[a];
+    g->axNinp = (g->axNin + 15) / 16 * 16;
+    g->axNoutp = (g->axNout + 15) / 16 * 16;
     return g;
 }
 
