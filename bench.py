@@ -137,6 +137,16 @@ def run_gpu(args, wl):
     gy32 = torch.from_numpy(gy).to(dev)
     results = {}
     outputs = {}
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] copy calibration: 1 GiB read + 1 GiB written by one copy kernel")
+        del a, b
+        torch.cuda.empty_cache()
     for dt_name, code in (("bf16", fno.FNO_BF16), ("f32", fno.FNO_F32)):
         if dt_name == "f32" and args.no_fp32:
             continue
@@ -206,6 +216,8 @@ def main():
     ap.add_argument("--workload", default="co2_block_128^3x32", choices=sorted(WORKLOADS))
     ap.add_argument("--no-oracle", action="store_true", help="skip the FP64 oracle (errors and cpu_baseline)")
     ap.add_argument("--no-fp32", action="store_true", help="time the BF16 path only")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",

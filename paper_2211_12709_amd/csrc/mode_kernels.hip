@@ -145,19 +145,32 @@ __global__ void __launch_bounds__(256) k_pw_wgrad_partial(const float *__restric
     }
 }
 
-// gw_pw[o][i] (+)= sum_c part[c][o][i]; gb[o] (+)= sum_c part[c][o][Ci].  Fixed order.
-__global__ void k_pw_wgrad_reduce(const float *__restrict__ part, float *__restrict__ gwpw, float *__restrict__ gb,
-                                  int Ci, int Co, int nchunk, int accumulate)
+// gw_pw[o][i] (+)= sum_c part[c][o][i]; gb[o] (+)= sum_c part[c][o][Ci].
+// One workgroup per (o, i) entry; a fixed-order tree over the chunks keeps the
+// result deterministic.
+__global__ void __launch_bounds__(256) k_pw_wgrad_reduce(const float *__restrict__ part, float *__restrict__ gwpw,
+                                                         float *__restrict__ gb, int Ci, int Co, int nchunk,
+                                                         int accumulate)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= Co * (Ci + 1)) return;
+    const int e = blockIdx.x;
     const int o = e / (Ci + 1), i = e % (Ci + 1);
+    const long long stride = (long long)Co * (Ci + 1);
     float s = 0.f;
-    for (int c = 0; c < nchunk; c++) s += part[((long long)c * Co + o) * (Ci + 1) + i];
-    if (i < Ci) {
-        if (gwpw) gwpw[o * Ci + i] = (accumulate ? gwpw[o * Ci + i] : 0.f) + s;
-    } else {
-        if (gb) gb[o] = (accumulate ? gb[o] : 0.f) + s;
+    for (int c = threadIdx.x; c < nchunk; c += 256) s += part[c * stride + e];
+    __shared__ float red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        s = red[0];
+        if (i < Ci) {
+            if (gwpw) gwpw[o * Ci + i] = (accumulate ? gwpw[o * Ci + i] : 0.f) + s;
+        } else {
+            if (gb) gb[o] = (accumulate ? gb[o] : 0.f) + s;
+        }
     }
 }
 
@@ -202,15 +215,15 @@ void launch_pw_wgrad(const float *gz, const T *x, float *part, float *gwpw, floa
     const long long chunk = 65536;
     const int nchunk = pw_wgrad_chunks(total);
     hipLaunchKernelGGL(k_pw_wgrad_partial<T>, dim3(nchunk, Co), dim3(256), 0, st, gz, x, part, B, Ci, Co, ncell, chunk);
-    hipLaunchKernelGGL(k_pw_wgrad_reduce, dim3((Co * (Ci + 1) + 255) / 256), dim3(256), 0, st, part, gwpw, gb, Ci, Co,
-                       nchunk, accumulate);
+    hipLaunchKernelGGL(k_pw_wgrad_reduce, dim3(Co * (Ci + 1)), dim3(256), 0, st, part, gwpw, gb, Ci, Co, nchunk,
+                       accumulate);
 }
 
 void launch_pw_reduce(const float *part, float *gwpw, float *gb, int Ci, int Co, int nchunk, int accumulate,
                       hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pw_wgrad_reduce, dim3((Co * (Ci + 1) + 255) / 256), dim3(256), 0, st, part, gwpw, gb, Ci, Co,
-                       nchunk, accumulate);
+    hipLaunchKernelGGL(k_pw_wgrad_reduce, dim3(Co * (Ci + 1)), dim3(256), 0, st, part, gwpw, gb, Ci, Co, nchunk,
+                       accumulate);
 }
 
 template void launch_pw_wgrad<float>(const float *, const float *, float *, float *, float *, int, int, int, long long,
