@@ -51,7 +51,8 @@ bool zt_supported(const Dims &d, int dtype);
 int zt_grid(const Dims &d);
 template <typename T>
 hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const float2 *u, T *out, const T *src, const T *gy,
-                     const float *wpw, const float *bpw, float *part, const ZtTabs &tb, int accumulate, hipStream_t st);
+                     const float *wpw, const float *bpw, float *part, const ZtTabs &tb, int accumulate, hipStream_t st,
+                     int *grid_used = nullptr);
 template <typename TC>
 hipError_t launch_axis_mfma(const float2 *in, float2 *out, const void *tab, const void *tab_lo, long long outer,
                             int Nin, int Nout, long long cols, hipStream_t st);
@@ -374,12 +375,13 @@ static int block_bwd_impl(const fno_plan_t *p, const void *x_, const void *cache
     inverse_xy(p, nullptr, d.Co, const_cast<float2 *>(u2), t1, st, true);
     if (zt_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
         T *gzt = (T *)gz;  // gz stored in the activation type
+        int grid_used = zt_grid(d);
         FNO_TIMED(p, st, "zt_bwd",
                   (void)launch_zt<T>(ZEPI_BWD, d, d.Co, d.Ci, t1, gzt, x, (const T *)gy_, wpw, bpw, part,
-                                     zt_tabs<T>(p, false), 0, st));
+                                     zt_tabs<T>(p, false), 0, st, &grid_used));
         if (gwpw_ || gb_)
             FNO_TIMED(p, st, "pw_reduce",
-                      launch_pw_reduce(part, (float *)gwpw_, (float *)gb_, d.Ci, d.Co, zt_grid(d) * 4, accumulate, st));
+                      launch_pw_reduce(part, (float *)gwpw_, (float *)gb_, d.Ci, d.Co, grid_used * 4, accumulate, st));
         forward_spectrum<T>(p, gzt, d.Co, p->tab.wt_inv, t1, t2, gyh, st);
         FNO_TIMED(p, st, "mix_bwd",
                   launch_mix_bwd(xh, (const float2 *)w_, gyh, gxh, (float2 *)gw_, d.B, d.Ci, d.Co, d.nmode, accumulate,

@@ -97,4 +97,37 @@ __device__ __forceinline__ float gelu_grad_f(float u)
     return 0.5f * (1.0f + erff(u * 0.70710678118654752f)) + u * 0.39894228040143268f * expf(-0.5f * u * u);
 }
 
+// GELU and its derivative from one evaluation of erf by Abramowitz & Stegun,
+// Handbook of Mathematical Functions, formula 7.1.26:
+//   erf(x) = 1 - (a1 s + a2 s^2 + a3 s^3 + a4 s^4 + a5 s^5) exp(-x^2),  s = 1/(1 + p x),  x >= 0,
+// with absolute error at most 1.5e-7.  exp(-x^2) at x = u/sqrt(2) is also the
+// Gaussian density term of GELU'(u) = Phi(u) + u phi(u), so both cost one
+// exponential and one reciprocal.
+__device__ __forceinline__ void gelu_as(float u, float &g, float &dg)
+{
+    const float x = u * 0.70710678118654752f;
+    const float ax = fabsf(x);
+    const float s = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+    const float poly =
+        s * fmaf(s, fmaf(s, fmaf(s, fmaf(s, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
+    const float e = __expf(-ax * ax);
+    const float erf_ax = fmaf(-poly, e, 1.0f);
+    const float erfx = __builtin_copysignf(erf_ax, x);
+    const float phi_cdf = fmaf(0.5f, erfx, 0.5f);
+    g = u * phi_cdf;
+    dg = fmaf(u * 0.39894228040143268f, e, phi_cdf);
+}
+__device__ __forceinline__ float gelu_fast(float u)
+{
+    float g, dg;
+    gelu_as(u, g, dg);
+    return g;
+}
+__device__ __forceinline__ float gelu_grad_fast(float u)
+{
+    float g, dg;
+    gelu_as(u, g, dg);
+    return dg;
+}
+
 }  // namespace fno

@@ -24,17 +24,10 @@ struct TzyArgs {
     int NQ, NZB, KB, MZ, MY, Yc, QY, NYC;
 };
 
-// Accumulator tile i of a wave: column block w + 4 (i / MY); within it, tile
-// pairs (2p, 2p + 1) are the re and im row blocks p and p + MY/2.
-__device__ __forceinline__ int tile_mb(int i, int MY)
-{
-    const int rem = i % MY;
-    return (rem & 1) * (MY >> 1) + (rem >> 1);
-}
-
 // NTT: N tiles of the t/z steps (1: Kt <= 8, re|im in one tile; 2: Kt <= 16).
-// MAXT: accumulator tiles per wave in the y step.  NZBM: max z blocks (Nz <= 16*NZBM).
-template <typename T, int NTT, bool SPLIT, int MAXT, int NZBM, int MAXKB>
+// MY: row tiles of the y step (2 ceil(Ky/16)); NBW: its column tiles per wave.
+// NZBM: max z blocks (Nz <= 16*NZBM); MAXKB: max kz blocks.
+template <typename T, int NTT, bool SPLIT, int MY, int NBW, int NZBM, int MAXKB>
 __global__ void __launch_bounds__(256) k_tzy_fwd(const T *__restrict__ x, float2 *__restrict__ t2,
                                                  const typename OpOf<T>::type *__restrict__ tabT,
                                                  const typename OpOf<T>::type *__restrict__ tabT_lo,
@@ -69,9 +62,11 @@ __global__ void __launch_bounds__(256) k_tzy_fwd(const T *__restrict__ x, float2
             if (SPLIT) tbl[q][nt] = q < a.NQ ? tabT_lo[(q * NTT + nt) * 64 + lane] : op_zero<T>();
         }
 
-    f4v acc[MAXT];
+    f4v acc[NBW][MY];  // y-step tiles: column block w + 4 nbi, row block mb (re rows < MY/2 <= im rows)
 #pragma unroll
-    for (int i = 0; i < MAXT; i++) acc[i] = f4_zero();
+    for (int nbi = 0; nbi < NBW; nbi++)
+#pragma unroll
+        for (int mb = 0; mb < MY; mb++) acc[nbi][mb] = f4_zero();
     const int NT2 = (ncol + 15) / 16;
     const int per_wave = a.Yc / 4;  // planes per wave per chunk
 
@@ -177,17 +172,26 @@ __global__ void __launch_bounds__(256) k_tzy_fwd(const T *__restrict__ x, float2
             // chunk complete: y step over its 2*Yc K values
             const int ych = s / per_wave;
             __syncthreads();
+            for (int q = 0; q < a.QY; q++) {
+                Op ay[MY], ayl[MY];
 #pragma unroll
-            for (int i = 0; i < MAXT; i++) {
-                const int mb = tile_mb(i, a.MY), nb = w + 4 * (i / a.MY);
-                if (nb < NT2) {
-                    const int col = nb * 16 + c;
-                    for (int q = 0; q < a.QY; q++) {
-                        const Op ay = tabY[((ych * a.QY + q) * a.MY + mb) * 64 + lane];
+                for (int mb = 0; mb < MY; mb++) {
+                    const int ti = ((ych * a.QY + q) * MY + mb) * 64 + lane;
+                    ay[mb] = tabY[ti];
+                    if (SPLIT) ayl[mb] = tabY_lo[ti];
+                }
+#pragma unroll
+                for (int nbi = 0; nbi < NBW; nbi++) {
+                    const int nb = w + 4 * nbi;
+                    if (nb < NT2) {
+                        const int col = nb * 16 + c;
                         const Op bt = col < ncol ? *reinterpret_cast<const Op *>(tl + col * ldk + 16 * q + 4 * g)
                                                  : op_zero<T>();
-                        acc[i] = mma16(ay, bt, acc[i]);
-                        if (SPLIT) acc[i] = mma16(tabY_lo[((ych * a.QY + q) * a.MY + mb) * 64 + lane], bt, acc[i]);
+#pragma unroll
+                        for (int mb = 0; mb < MY; mb++) {
+                            acc[nbi][mb] = mma16(ay[mb], bt, acc[nbi][mb]);
+                            if (SPLIT) acc[nbi][mb] = mma16(ayl[mb], bt, acc[nbi][mb]);
+                        }
                     }
                 }
             }
@@ -195,29 +199,35 @@ __global__ void __launch_bounds__(256) k_tzy_fwd(const T *__restrict__ x, float2
         }
     };
 
-    Op xa[NZBM][2], xb[NZBM][2];
-    load_plane(plane_y(0), xa);
-    for (int s = 0; s < nplanes; s += 2) {  // nplanes is even: ping-pong without register copies
-        load_plane(plane_y(s + 1), xb);
-        do_plane(s, xa);
-        chunk_end(s);
-        if (s + 2 < nplanes) load_plane(plane_y(s + 2), xa);
-        do_plane(s + 1, xb);
-        chunk_end(s + 1);
+    // rotating register buffers: DEPTH planes are in flight while one is processed
+    constexpr int DEPTH = sizeof(T) == 2 ? 4 : 2;
+    Op xb[DEPTH][NZBM][2];
+#pragma unroll
+    for (int k = 0; k < DEPTH; k++) load_plane(plane_y(k), xb[k]);
+    for (int s0 = 0; s0 < nplanes; s0 += DEPTH) {  // nplanes is a multiple of DEPTH
+#pragma unroll
+        for (int k = 0; k < DEPTH; k++) {
+            const int s = s0 + k;
+            do_plane(s, xb[k]);
+            chunk_end(s);
+            if (s + DEPTH < nplanes) load_plane(plane_y(s + DEPTH), xb[k]);
+        }
     }
 
-    // write T2[slab][ky][(kz, kt)] as (re, im): tile i (even) holds re rows, tile i + 1 the matching im rows
+    // write T2[slab][ky][(kz, kt)] as (re, im): row block mb holds re rows, mb + MY/2 the matching im rows
 #pragma unroll
-    for (int i = 0; i < MAXT; i += 2) {
-        const int mb = tile_mb(i, a.MY), nb = w + 4 * (i / a.MY);
+    for (int nbi = 0; nbi < NBW; nbi++) {
+        const int nb = w + 4 * nbi;
         if (nb < NT2) {
             const int col = nb * 16 + c;
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int ky = mb * 16 + 4 * g + r;
-                if (ky < a.Ky && col < ncol)
-                    t2[(slab * a.Ky + ky) * (long long)ncol + col] = make_float2(acc[i][r], acc[i + 1][r]);
-            }
+            for (int mb = 0; mb < MY / 2; mb++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int ky = mb * 16 + 4 * g + r;
+                    if (ky < a.Ky && col < ncol)
+                        t2[(slab * a.Ky + ky) * (long long)ncol + col] = make_float2(acc[nbi][mb][r], acc[nbi][mb + MY / 2][r]);
+                }
         }
     }
 }
@@ -234,13 +244,14 @@ size_t tzy_lds_bytes(const TzyArgs &a, int elem, bool split)
     return zf + tl;
 }
 
-template <typename T, int NTT, bool SPLIT, int MAXT>
+template <typename T, int NTT, int MY, int NBW>
 static hipError_t launch_tzy_t(const T *x, float2 *t2, long long slabs, const TzyTabs &tb, const TzyArgs &a,
                                hipStream_t st)
 {
     typedef typename OpOf<T>::type Op;
+    constexpr bool SPLIT = sizeof(T) == 2;  // bfloat16 kernels use the hi/lo basis
     const size_t lds = tzy_lds_bytes(a, sizeof(T), SPLIT);
-    auto kern = k_tzy_fwd<T, NTT, SPLIT, MAXT, 8, 4>;
+    auto kern = k_tzy_fwd<T, NTT, SPLIT, MY, NBW, 8, 4>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -249,17 +260,25 @@ static hipError_t launch_tzy_t(const T *x, float2 *t2, long long slabs, const Tz
     return hipGetLastError();
 }
 
+// (row tiles, column tiles per wave) of the y step
+static void tzy_tiles(const Dims &d, int &MY, int &NBW)
+{
+    MY = 2 * ((d.K[1] + 15) / 16);
+    const int NT2 = (d.K[2] * d.K[3] + 15) / 16;
+    NBW = (NT2 + 3) / 4;
+}
+
 // Whether the MFMA path covers these dimensions.
 bool tzy_supported(const Dims &d, int dtype)
 {
     const int Nt = d.N[3], Nz = d.N[2];
     if (Nt % 4 != 0 || Nt > 32 || Nz > 128 || d.K[3] > 16 || d.K[2] > 64) return false;
-    const int Kzp = (d.K[2] + 15) / 16 * 16, Kyp = (d.K[1] + 15) / 16 * 16;
-    const int MY = 2 * Kyp / 16, NT2 = (d.K[2] * d.K[3] + 15) / 16;
-    if (MY * ((NT2 + 3) / 4) > 32) return false;
+    int MY, NBW;
+    tzy_tiles(d, MY, NBW);
+    if (MY > 8 || NBW > 8 || MY * NBW > 32 || (MY > 4 && NBW > 4)) return false;
     TzyArgs a{};
     a.NZB = (Nz + 15) / 16;
-    a.MZ = 2 * Kzp / 16;
+    a.MZ = 2 * ((d.K[2] + 15) / 16);
     a.Kz = d.K[2];
     a.Kt = d.K[3];
     a.Yc = dtype == FNO_BF16 ? 32 : 16;
@@ -286,20 +305,27 @@ TzyArgs tzy_args(const Dims &d, int dtype)
     return a;
 }
 
+template <typename T, int NTT>
+static hipError_t launch_tzy_n(const T *x, float2 *t2, long long slabs, const TzyTabs &tb, const TzyArgs &a, int MY,
+                               int NBW, hipStream_t st)
+{
+    if (MY == 2) return NBW <= 4 ? launch_tzy_t<T, NTT, 2, 4>(x, t2, slabs, tb, a, st)
+                                 : launch_tzy_t<T, NTT, 2, 8>(x, t2, slabs, tb, a, st);
+    if (MY == 4) return NBW <= 4 ? launch_tzy_t<T, NTT, 4, 4>(x, t2, slabs, tb, a, st)
+                                 : launch_tzy_t<T, NTT, 4, 8>(x, t2, slabs, tb, a, st);
+    if (MY == 6) return launch_tzy_t<T, NTT, 6, 4>(x, t2, slabs, tb, a, st);
+    return launch_tzy_t<T, NTT, 8, 4>(x, t2, slabs, tb, a, st);
+}
+
 template <typename T>
 hipError_t launch_tzy(const T *x, float2 *t2, long long slabs, const TzyTabs &tb, const Dims &d, hipStream_t st)
 {
     const int dtype = sizeof(T) == 2 ? FNO_BF16 : FNO_F32;
     const TzyArgs a = tzy_args(d, dtype);
-    const int NT2 = (a.Kz * a.Kt + 15) / 16;
-    const int tiles = a.MY * ((NT2 + 3) / 4);
-    constexpr bool split = sizeof(T) == 2;  // bfloat16 kernels use the hi/lo basis
-    if (d.K[3] <= 8) {
-        if (tiles <= 16) return launch_tzy_t<T, 1, split, 16>(x, t2, slabs, tb, a, st);
-        return launch_tzy_t<T, 1, split, 32>(x, t2, slabs, tb, a, st);
-    }
-    if (tiles <= 16) return launch_tzy_t<T, 2, split, 16>(x, t2, slabs, tb, a, st);
-    return launch_tzy_t<T, 2, split, 32>(x, t2, slabs, tb, a, st);
+    int MY, NBW;
+    tzy_tiles(d, MY, NBW);
+    if (d.K[3] <= 8) return launch_tzy_n<T, 1>(x, t2, slabs, tb, a, MY, NBW, st);
+    return launch_tzy_n<T, 2>(x, t2, slabs, tb, a, MY, NBW, st);
 }
 
 template hipError_t launch_tzy<float>(const float *, float2 *, long long, const TzyTabs &, const Dims &, hipStream_t);

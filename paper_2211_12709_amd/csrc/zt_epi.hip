@@ -83,17 +83,23 @@ __global__ void __launch_bounds__(256) k_zt_epi(const float2 *__restrict__ u, T 
 {
     typedef typename OpOf<T>::type Op;
     constexpr bool PW = EPI != ZEPI_PLAIN;
+    constexpr int ZC = 16;  // z values per chunk
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
-    const int Nz = a.Nz, Nt = a.Nt, Kz = a.Kz, Kt = a.Kt, Kzp = a.Kzp, Cs = a.Cs;
+    const int Nz = a.Nz, Nt = a.Nt, Kz = a.Kz, Kt = a.Kt, Kzp = a.Kzp, Cs = a.Cs, Csrc = a.Csrc;
     const long long nxy = (long long)a.Nx * a.Ny, plane = (long long)Nz * Nt, ncell = nxy * plane;
 
-    // LDS: U planes [Cs][Kt][Kzp] re then im; V chunk [ZC][Cs][ldv]
+    // LDS: U planes [Cs][Kt][Kzp] re then im; V chunk [ZC][Cs][ldv]; source chunk [ci][ZC][Ntp]
     const int ldv = 16 * NTT + 4;
+    const int Ntp = 16 * a.NTQ;
+    const int ldxc = ZC * Ntp + 4;  // source channel stride (padded against bank conflicts)
     T *ure = reinterpret_cast<T *>(smem);
     T *uim = ure + (size_t)Cs * Kt * Kzp;
     T *vl = uim + (size_t)Cs * Kt * Kzp;
+    T *xl = vl + (size_t)ZC * Cs * ldv;
     for (int i = threadIdx.x; i < 2 * Cs * Kt * Kzp; i += 256) ure[i] = from_f32<T>(0.f);
+    if (PW)
+        for (int i = threadIdx.x; i < Csrc * ldxc; i += 256) xl[i] = from_f32<T>(0.f);
 
     // constant fragments: t basis (A of phase 2), pointwise weights (B of phase 2)
     Op ta[2][NTT], tal[2][NTT];
@@ -114,9 +120,9 @@ __global__ void __launch_bounds__(256) k_zt_epi(const float2 *__restrict__ u, T 
             for (int j = 0; j < 4; j++) {
                 const int ci = 16 * qi + 4 * g + j, co = 16 * nc + c;
                 float x = 0.f;
-                if (PW && ci < a.Csrc && co < Cs) {
+                if (PW && ci < Csrc && co < Cs) {
                     // BLOCK/BWD: co = o, ci = i: W_pw[o][i];  ADJ: co = i, ci = o: W_pw[o][i]
-                    x = EPI == ZEPI_ADJ ? wpw[ci * Cs + co] : wpw[co * a.Csrc + ci];
+                    x = EPI == ZEPI_ADJ ? wpw[ci * Cs + co] : wpw[co * Csrc + ci];
                 }
                 v[j] = x;
             }
@@ -138,25 +144,57 @@ __global__ void __launch_bounds__(256) k_zt_epi(const float2 *__restrict__ u, T 
 #pragma unroll
     for (int nc = 0; nc < MAXC; nc++) gbacc[nc] = 0.f;
 
+    // source chunk staging: thread -> fixed (zl, t4) pair (4 consecutive t), channels strided
+    const int nt4 = Nt / 4, npair = ZC * nt4;
+    const int sp_cstep = 256 / npair;  // threads per pair (>= 2 since Nt <= 32)
+    const bool sp_ok = (int)threadIdx.x < sp_cstep * npair;
+    const int sp_pair = threadIdx.x % npair, sp_c0 = threadIdx.x / npair;
+    const int sp_zl = sp_pair / nt4, sp_t4 = sp_pair % nt4;
     const long long nplanes = (long long)a.B * nxy;
     for (long long pl = blockIdx.x; pl < nplanes; pl += gridDim.x) {
         const int b = (int)(pl / nxy);
         const long long xy = pl % nxy;
-        __syncthreads();  // previous plane's readers of U and V are done
-        // ---- phase 0: U of every channel, transposed to [c][kt][kz]
-        for (int e = threadIdx.x; e < Cs * Kz * Kt; e += 256) {
-            const int cs = e / (Kz * Kt), r = e % (Kz * Kt), kz = r / Kt, kt = r % Kt;
-            const float2 v = u[(((long long)b * Cs + cs) * nxy + xy) * Kz * Kt + r];
-            ure[((size_t)cs * Kt + kt) * Kzp + kz] = from_f32<T>(v.x);
-            uim[((size_t)cs * Kt + kt) * Kzp + kz] = from_f32<T>(v.y);
+        const T *srcp = src + (long long)b * Csrc * ncell + xy * plane;
+        __syncthreads();  // previous plane's readers of U are done
+        // ---- phase 0: U of every channel, transposed to [c][kt][kz]; thread owns fixed (kz, kt) pairs
+        for (int r = threadIdx.x; r < Kz * Kt; r += 256) {
+            const int kz = r / Kt, kt = r - (r / Kt) * Kt;
+            const float2 *up = u + ((long long)b * Cs * nxy + xy) * Kz * Kt + r;
+            T *ur = ure + (size_t)kt * Kzp + kz, *ui = uim + (size_t)kt * Kzp + kz;
+            for (int cs = 0; cs < Cs; cs++) {
+                const float2 v = up[(long long)cs * nxy * Kz * Kt];
+                ur[(size_t)cs * Kt * Kzp] = from_f32<T>(v.x);
+                ui[(size_t)cs * Kt * Kzp] = from_f32<T>(v.y);
+            }
         }
-        for (int zc0 = 0; zc0 < Nz; zc0 += a.ZC) {
-            __syncthreads();  // U staged / previous chunk's V consumed
-            // ---- phase 1: V^T tiles (channel cs, z tile zt) into LDS
-            const int nzt = (min(a.ZC, Nz - zc0) + 15) / 16;
-            for (int task = w; task < Cs * nzt; task += 4) {
-                const int cs = task / nzt, zt = task % nzt;
-                const int zg = zc0 / 16 + zt;  // global z tile
+        for (int zc0 = 0; zc0 < Nz; zc0 += ZC) {
+            __syncthreads();  // U staged / previous chunk's V and source consumed
+            // source chunk -> LDS [ci][zl][t]: thread owns pair (zl, t4), strides over channels
+            if (PW && sp_ok && zc0 + sp_zl < Nz) {
+                const T *sp = srcp + (long long)(zc0 + sp_zl) * Nt + 4 * sp_t4;
+                T *dl = xl + sp_zl * Ntp + 4 * sp_t4;
+                for (int ci0 = sp_c0; ci0 < Csrc; ci0 += 4 * sp_cstep) {
+                    Op vv[4];
+#pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                        const int ci = ci0 + k * sp_cstep;
+                        vv[k] = ci < Csrc ? *reinterpret_cast<const Op *>(sp + (long long)ci * ncell) : op_zero<T>();
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                        const int ci = ci0 + k * sp_cstep;
+                        if (ci < Csrc) *reinterpret_cast<Op *>(dl + (size_t)ci * ldxc) = vv[k];
+                    }
+                }
+            } else if (PW && sp_ok) {
+                // z beyond the grid: zeros
+                T *dl = xl + sp_zl * Ntp + 4 * sp_t4;
+                for (int ci = sp_c0; ci < Csrc; ci += sp_cstep)
+                    *reinterpret_cast<Op *>(dl + (size_t)ci * ldxc) = op_zero<T>();
+            }
+            // ---- phase 1: V^T tiles (channel cs) of this z tile into LDS
+            const int zg = zc0 / 16;
+            for (int cs = w; cs < Cs; cs += 4) {
 #pragma unroll
                 for (int mt = 0; mt < NTT; mt++) {
                     const int ri = NTT == 1 ? (c >> 3) : mt;
@@ -177,17 +215,15 @@ __global__ void __launch_bounds__(256) k_zt_epi(const float2 *__restrict__ u, T 
                         acc = mma16(av, tabZ[ti], acc);
                         if (SPLIT) acc = mma16(av, tabZ_lo[ti], acc);
                     }
-                    // acc[r] = V^T[(ri, kt) = 16 mt + 4 g + r][z = 16 zt + c]
-                    const int zl = 16 * zt + c;
-                    if (zl < a.ZC) {
-                        float v[4] = {acc[0], acc[1], acc[2], acc[3]};
-                        store4(vl + ((size_t)zl * Cs + cs) * ldv + 16 * mt + 4 * g, v);
-                    }
+                    // acc[r] = V^T[(ri, kt) = 16 mt + 4 g + r][z = zc0 + c]
+                    float v[4] = {acc[0], acc[1], acc[2], acc[3]};
+                    store4(vl + ((size_t)c * Cs + cs) * ldv + 16 * mt + 4 * g, v);
                 }
             }
             __syncthreads();
-            // ---- phase 2: per z, Out^T[t][co] and the epilogue
-            for (int zl = w; zl < a.ZC && zc0 + zl < Nz; zl += 4) {
+            // ---- phase 2: per z, Out^T[t][co] and the epilogue (two z in flight per wave)
+#pragma unroll 2
+            for (int zl = w; zl < ZC && zc0 + zl < Nz; zl += 4) {
                 const int z = zc0 + zl;
                 f4v acc[2][MAXC];
 #pragma unroll
@@ -211,20 +247,17 @@ __global__ void __launch_bounds__(256) k_zt_epi(const float2 *__restrict__ u, T 
                 if (PW) {
 #pragma unroll
                     for (int qi = 0; qi < MAXC; qi++) {
-                        if (16 * qi < a.Csrc) {
+                        if (16 * qi < Csrc) {
 #pragma unroll
                             for (int mt = 0; mt < 2; mt++) {
                                 if (mt < a.NTQ) {
-                                    const int t = 16 * mt + c;
-                                    float v[4];
+                                    // A[t = 16 mt + c][ci = 16 qi + 4 g + j]
+                                    const int ci0 = 16 * qi + 4 * g;
+                                    const T *xr = xl + (size_t)ci0 * ldxc + zl * Ntp + 16 * mt + c;
+                                    float xv[4];
 #pragma unroll
-                                    for (int j = 0; j < 4; j++) {
-                                        const int ci = 16 * qi + 4 * g + j;
-                                        v[j] = (ci < a.Csrc && t < Nt)
-                                                   ? to_f32(src[((long long)b * a.Csrc + ci) * ncell + xy * plane + (long long)z * Nt + t])
-                                                   : 0.f;
-                                    }
-                                    const Op av = op_from4<T>(v[0], v[1], v[2], v[3]);
+                                    for (int j = 0; j < 4; j++) xv[j] = ci0 + j < Csrc ? to_f32(xr[j * ldxc]) : 0.f;
+                                    const Op av = op_from4<T>(xv[0], xv[1], xv[2], xv[3]);
 #pragma unroll
                                     for (int nc = 0; nc < MAXC; nc++) acc[mt][nc] = mma16(av, wb[qi][nc], acc[mt][nc]);
                                 }
@@ -245,13 +278,13 @@ __global__ void __launch_bounds__(256) k_zt_epi(const float2 *__restrict__ u, T 
                         for (int r = 0; r < 4; r++) v[r] = acc[mt][nc][r];
                         if (EPI == ZEPI_BLOCK) {
 #pragma unroll
-                            for (int r = 0; r < 4; r++) v[r] = gelu_f(v[r] + bias[nc]);
+                            for (int r = 0; r < 4; r++) v[r] = gelu_fast(v[r] + bias[nc]);
                         } else if (EPI == ZEPI_BWD) {
                             float gv[4] = {0.f, 0.f, 0.f, 0.f};
                             if (ok) load4(gy + idx, gv);
 #pragma unroll
                             for (int r = 0; r < 4; r++) {
-                                v[r] = ok ? gv[r] * gelu_grad_f(v[r] + bias[nc]) : 0.f;
+                                v[r] = ok ? gv[r] * gelu_grad_fast(v[r] + bias[nc]) : 0.f;
                                 gbacc[nc] += v[r];
                             }
                             // keep the gradient tile for the weight-gradient product
@@ -277,11 +310,11 @@ __global__ void __launch_bounds__(256) k_zt_epi(const float2 *__restrict__ u, T 
                             for (int nc = 0; nc < MAXC; nc++) bg[nc] = to_op<T>(acc[mt][nc]);
 #pragma unroll
                             for (int mi = 0; mi < MAXC; mi++) {
-                                const int i = 16 * mi + c, t0 = 16 * mt + 4 * g;
-                                float xv[4] = {0.f, 0.f, 0.f, 0.f};
-                                if (i < a.Csrc && t0 < Nt)
-                                    load4(src + ((long long)b * a.Csrc + i) * ncell + xy * plane + (long long)z * Nt + t0, xv);
-                                const Op ax = op_from4<T>(xv[0], xv[1], xv[2], xv[3]);
+                                // A[i = 16 mi + c][t = 16 mt + 4 g + j] from the staged source (zero beyond Csrc)
+                                const Op ax = 16 * mi + c < Csrc
+                                                  ? *reinterpret_cast<const Op *>(xl + (size_t)(16 * mi + c) * ldxc +
+                                                                                  zl * Ntp + 16 * mt + 4 * g)
+                                                  : op_zero<T>();
 #pragma unroll
                                 for (int nc = 0; nc < MAXC; nc++) gwacc[mi][nc] = mma16(ax, bg[nc], gwacc[mi][nc]);
                             }
@@ -293,7 +326,7 @@ __global__ void __launch_bounds__(256) k_zt_epi(const float2 *__restrict__ u, T 
     }
     if (EPI == ZEPI_BWD) {
         // partial sums of this wave: part[(block * 4 + w)][o][0..Ci-1] = gw, [o][Ci] = gb
-        const int Ci = a.Csrc, Co = Cs;
+        const int Ci = Csrc, Co = Cs;
         float *pw = part + ((size_t)blockIdx.x * 4 + w) * Co * (Ci + 1);
 #pragma unroll
         for (int mi = 0; mi < MAXC; mi++)
@@ -322,7 +355,9 @@ struct ZtTabs {
 
 static size_t zt_lds_bytes(const ZtArgs &a, int elem, int ntt)
 {
-    return ((size_t)2 * a.Cs * a.Kt * a.Kzp + (size_t)a.ZC * a.Cs * (16 * ntt + 4)) * elem;
+    const int ZC = 16, Ntp = 16 * ((a.Nt + 15) / 16);
+    return ((size_t)2 * a.Cs * a.Kt * a.Kzp + (size_t)ZC * a.Cs * (16 * ntt + 4) +
+            (size_t)a.Csrc * (ZC * Ntp + 4)) * elem;
 }
 
 bool zt_supported(const Dims &d, int dtype)
@@ -332,8 +367,10 @@ bool zt_supported(const Dims &d, int dtype)
     ZtArgs a{};
     a.Cs = std::max(d.Ci, d.Co);
     a.Kt = d.K[3];
+    a.Nt = d.N[3];
     a.Kzp = (d.K[2] + 15) / 16 * 16;
-    a.ZC = 32;
+    a.Csrc = std::max(d.Ci, d.Co);
+    a.ZC = 16;
     return zt_lds_bytes(a, dtype == FNO_BF16 ? 2 : 4, d.K[3] <= 8 ? 1 : 2) <= 160 * 1024;
 }
 
@@ -341,7 +378,8 @@ int zt_grid(const Dims &d) { return (int)std::min<long long>((long long)d.B * d.
 
 template <typename T, int EPI, int NTT, int MAXC>
 static hipError_t launch_zt_t(const ZtArgs &a, const float2 *u, T *out, const T *src, const T *gy, const float *wpw,
-                              const float *bpw, float *part, const ZtTabs &tb, int grid, hipStream_t st)
+                              const float *bpw, float *part, const ZtTabs &tb, int grid, hipStream_t st,
+                              int *grid_used)
 {
     typedef typename OpOf<T>::type Op;
     constexpr bool split = sizeof(T) == 2;
@@ -350,6 +388,14 @@ static hipError_t launch_zt_t(const ZtArgs &a, const float2 *u, T *out, const T 
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    // persistent grid: as many workgroups as can be resident at once (at most `grid`)
+    int per_cu = 0, dev = 0, ncu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), 256, lds) ==
+            hipSuccess &&
+        hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && per_cu > 0)
+        grid = std::min(grid, per_cu * ncu);
+    if (grid_used) *grid_used = grid;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(256), lds, st, u, out, src, gy, wpw, bpw, part, (const Op *)tb.z,
                        (const Op *)tb.z_lo, (const Op *)tb.t, (const Op *)tb.t_lo, a);
     return hipGetLastError();
@@ -358,20 +404,22 @@ static hipError_t launch_zt_t(const ZtArgs &a, const float2 *u, T *out, const T 
 template <typename T, int EPI>
 static hipError_t launch_zt_e(const ZtArgs &a, int ntt, int maxc, const float2 *u, T *out, const T *src, const T *gy,
                               const float *wpw, const float *bpw, float *part, const ZtTabs &tb, int grid,
-                              hipStream_t st)
+                              hipStream_t st, int *grid_used)
 {
     if (ntt == 1) {
-        if (maxc <= 2) return launch_zt_t<T, EPI, 1, 2>(a, u, out, src, gy, wpw, bpw, part, tb, grid, st);
-        return launch_zt_t<T, EPI, 1, 4>(a, u, out, src, gy, wpw, bpw, part, tb, grid, st);
+        if (maxc <= 2) return launch_zt_t<T, EPI, 1, 2>(a, u, out, src, gy, wpw, bpw, part, tb, grid, st, grid_used);
+        return launch_zt_t<T, EPI, 1, 4>(a, u, out, src, gy, wpw, bpw, part, tb, grid, st, grid_used);
     }
-    if (maxc <= 2) return launch_zt_t<T, EPI, 2, 2>(a, u, out, src, gy, wpw, bpw, part, tb, grid, st);
-    return launch_zt_t<T, EPI, 2, 4>(a, u, out, src, gy, wpw, bpw, part, tb, grid, st);
+    if (maxc <= 2) return launch_zt_t<T, EPI, 2, 2>(a, u, out, src, gy, wpw, bpw, part, tb, grid, st, grid_used);
+    return launch_zt_t<T, EPI, 2, 4>(a, u, out, src, gy, wpw, bpw, part, tb, grid, st, grid_used);
 }
 
 // epi: ZEPI_*; Cs = output/spectral channels, Csrc = pointwise source channels.
+// grid_used (nullable) receives the number of workgroups launched (rows of BWD partial sums / 4).
 template <typename T>
 hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const float2 *u, T *out, const T *src, const T *gy,
-                     const float *wpw, const float *bpw, float *part, const ZtTabs &tb, int accumulate, hipStream_t st)
+                     const float *wpw, const float *bpw, float *part, const ZtTabs &tb, int accumulate, hipStream_t st,
+                     int *grid_used)
 {
     ZtArgs a{};
     a.B = d.B;
@@ -386,24 +434,24 @@ hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const float2 *u, 
     a.Csrc = Csrc;
     a.QZ = 2 * a.Kzp / 16;
     a.NTQ = (d.N[3] + 15) / 16;
-    a.ZC = 32;
+    a.ZC = 16;
     a.accumulate = accumulate;
     const int ntt = d.K[3] <= 8 ? 1 : 2;
     const int maxc = (std::max(Cs, Csrc) + 15) / 16;
     const int grid = zt_grid(d);
     switch (epi) {
-    case ZEPI_PLAIN: return launch_zt_e<T, ZEPI_PLAIN>(a, ntt, maxc, u, out, src, gy, wpw, bpw, part, tb, grid, st);
-    case ZEPI_BLOCK: return launch_zt_e<T, ZEPI_BLOCK>(a, ntt, maxc, u, out, src, gy, wpw, bpw, part, tb, grid, st);
-    case ZEPI_BWD: return launch_zt_e<T, ZEPI_BWD>(a, ntt, maxc, u, out, src, gy, wpw, bpw, part, tb, grid, st);
-    default: return launch_zt_e<T, ZEPI_ADJ>(a, ntt, maxc, u, out, src, gy, wpw, bpw, part, tb, grid, st);
+    case ZEPI_PLAIN: return launch_zt_e<T, ZEPI_PLAIN>(a, ntt, maxc, u, out, src, gy, wpw, bpw, part, tb, grid, st, grid_used);
+    case ZEPI_BLOCK: return launch_zt_e<T, ZEPI_BLOCK>(a, ntt, maxc, u, out, src, gy, wpw, bpw, part, tb, grid, st, grid_used);
+    case ZEPI_BWD: return launch_zt_e<T, ZEPI_BWD>(a, ntt, maxc, u, out, src, gy, wpw, bpw, part, tb, grid, st, grid_used);
+    default: return launch_zt_e<T, ZEPI_ADJ>(a, ntt, maxc, u, out, src, gy, wpw, bpw, part, tb, grid, st, grid_used);
     }
 }
 
 template hipError_t launch_zt<float>(int, const Dims &, int, int, const float2 *, float *, const float *,
                                      const float *, const float *, const float *, float *, const ZtTabs &, int,
-                                     hipStream_t);
+                                     hipStream_t, int *);
 template hipError_t launch_zt<__bf16>(int, const Dims &, int, int, const float2 *, __bf16 *, const __bf16 *,
                                       const __bf16 *, const float *, const float *, float *, const ZtTabs &, int,
-                                      hipStream_t);
+                                      hipStream_t, int *);
 
 }  // namespace fno
