@@ -129,6 +129,40 @@ int fno_block_bwd(const fno_plan_t *plan, const void *x, const void *cache, cons
                   const void *w_pw, const void *b_pw, const void *gy, void *gx, void *gw,
                   void *gw_pw, void *gb_pw, int accumulate, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- Network glue of Alg. 1 (encoder, decoder, loss).  These act pointwise
+ * on the grid, so they take the number of grid points N instead of a plan.
+ * Activations are [B][C][N] in `dtype` (FNO_F32 / FNO_BF16), weights float,
+ * all device pointers 16-byte aligned; work is enqueued on `stream`.
+ * Weight gradients are deterministic (fixed-order two-stage sums). */
+
+/* Encoder (Alg. 1, lifting): y = GELU(w x + b), w [C_out][C_in], b [C_out]
+ * (nullable).  Limits: C_in <= 8, C_out <= 64. */
+int fno_lift_fwd(int32_t dtype, int32_t B, int32_t C_in, int32_t C_out, int64_t N, const void *x, const float *w,
+                 const float *b, void *y, void *stream);
+/* Weight gradients of the encoder: gw [C_out][C_in], gb [C_out] (each nullable);
+ * no input gradient (the encoder's input is data).  accumulate != 0 adds. */
+int fno_lift_bwd(int32_t dtype, int32_t B, int32_t C_in, int32_t C_out, int64_t N, const void *x, const float *w,
+                 const float *b, const void *gy, float *gw, float *gb, int accumulate, void *ws, size_t ws_bytes,
+                 void *stream);
+/* Decoder (Alg. 1, two pointwise layers): y = w2 GELU(w1 x + b1) + b2 with
+ * H hidden channels that are never stored; w1 [H][C_in], b1 [H], w2 [C_out][H],
+ * b2 [C_out] (biases nullable).  Limits: C_in <= 32, H <= 128, C_out == 1. */
+int fno_proj_fwd(int32_t dtype, int32_t B, int32_t C_in, int32_t H, int32_t C_out, int64_t N, const void *x,
+                 const float *w1, const float *b1, const float *w2, const float *b2, void *y, void *stream);
+/* Backward of the decoder: gx (required) and gw1, gb1, gw2, gb2 (nullable).
+ * accumulate != 0 adds into every output. */
+int fno_proj_bwd(int32_t dtype, int32_t B, int32_t C_in, int32_t H, int32_t C_out, int64_t N, const void *x,
+                 const float *w1, const float *b1, const float *w2, const float *b2, const void *gy, void *gx,
+                 float *gw1, float *gb1, float *gw2, float *gb2, int accumulate, void *ws, size_t ws_bytes,
+                 void *stream);
+/* Mean-squared error over n elements: *loss (device float) = mean((y - t)^2),
+ * gy (nullable) = 2 (y - t) / n. */
+int fno_mse(int32_t dtype, int64_t n, const void *y, const void *target, float *loss, void *gy, void *ws,
+            size_t ws_bytes, void *stream);
+/* Workspace bytes that fno_lift_bwd, fno_proj_bwd and fno_mse need (the
+ * largest of the three for these channel counts). */
+int fno_glue_workspace_bytes(int32_t C_in, int32_t H, int32_t C_out, size_t *out);
+
 /* Per-kernel timing (diagnostic, for benchmarks and profiles).  While enabled
  * on a plan, every kernel the plan launches is bracketed by two HIP events
  * recorded on the launch stream.  fno_timing_read waits for the recorded

@@ -411,6 +411,34 @@ static int block_bwd_impl(const fno_plan_t *p, const void *x_, const void *cache
 
 }  // namespace fno
 
+// ---------------------------------------------------------------- network glue
+namespace fno {
+int glue_blocks();
+size_t proj_part_len(int Ci, int H);
+void launch_sum_rows(const float *part, float *out, int len, size_t stride, int nchunk, int accumulate, hipStream_t st);
+template <typename T>
+hipError_t launch_lift_fwd(const T *x, T *y, const float *w, const float *b, int B, int Ci, int Co, long long N,
+                           hipStream_t st);
+template <typename T>
+hipError_t launch_lift_bwd(const T *x, const T *gy, const float *w, const float *b, float *part, float *gw, float *gb,
+                           int B, int Ci, int Co, long long N, int accumulate, hipStream_t st);
+template <typename T>
+hipError_t launch_proj(bool bwd, int B, int Ci, int H, int Co, long long N, const T *x, const T *gy, T *y_or_gx,
+                       const float *w1, const float *b1, const float *w2, const float *b2, float *part, int accumulate,
+                       hipStream_t st);
+template <typename T>
+hipError_t launch_mse(const T *y, const T *t, T *gy, float *part, float *loss, long long n, hipStream_t st);
+
+static size_t glue_ws(int Ci, int H, int Co)
+{
+    const size_t lift = (size_t)glue_blocks() * Co * (Ci + 1) * sizeof(float);
+    const size_t proj = (size_t)glue_blocks() * 4 * proj_part_len(Ci, H) * sizeof(float);
+    const size_t mse = (size_t)glue_blocks() * sizeof(float);
+    return std::max(std::max(lift, proj), mse);
+}
+static bool al16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+}  // namespace fno
+
 using namespace fno;
 
 extern "C" {
@@ -592,6 +620,110 @@ int fno_block_bwd(const fno_plan_t *plan, const void *x, const void *cache, cons
                                       ws_bytes, stream);
     return block_bwd_impl<float>(plan, x, cache, w, w_pw, b_pw, gy, gx, gw, gw_pw, gb_pw, accumulate, ws, ws_bytes,
                                  stream);
+}
+
+
+int fno_glue_workspace_bytes(int32_t C_in, int32_t H, int32_t C_out, size_t *out)
+{
+    if (!out || C_in < 1 || H < 1 || C_out < 1) return FNO_ERR_INVALID_ARG;
+    *out = glue_ws(C_in, std::max(H, 1), C_out);
+    return FNO_OK;
+}
+
+int fno_lift_fwd(int32_t dtype, int32_t B, int32_t C_in, int32_t C_out, int64_t N, const void *x, const float *w,
+                 const float *b, void *y, void *stream)
+{
+    if (B < 1 || C_in < 1 || C_out < 1 || N < 1 || !x || !w || !y) return FNO_ERR_INVALID_ARG;
+    if (dtype != FNO_F32 && dtype != FNO_BF16) return FNO_ERR_UNSUPPORTED;
+    if (C_in > 8 || C_out > 64) return FNO_ERR_UNSUPPORTED;
+    if (!al16(x) || !al16(w) || !al16(y) || (b && !al16(b))) return FNO_ERR_ALIGNMENT;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = dtype == FNO_BF16
+                       ? launch_lift_fwd<__bf16>((const __bf16 *)x, (__bf16 *)y, w, b, B, C_in, C_out, N, st)
+                       : launch_lift_fwd<float>((const float *)x, (float *)y, w, b, B, C_in, C_out, N, st);
+    return e == hipSuccess ? FNO_OK : FNO_ERR_HIP;
+}
+
+int fno_lift_bwd(int32_t dtype, int32_t B, int32_t C_in, int32_t C_out, int64_t N, const void *x, const float *w,
+                 const float *b, const void *gy, float *gw, float *gb, int accumulate, void *ws, size_t ws_bytes,
+                 void *stream)
+{
+    if (B < 1 || C_in < 1 || C_out < 1 || N < 1 || !x || !w || !gy || !ws) return FNO_ERR_INVALID_ARG;
+    if (dtype != FNO_F32 && dtype != FNO_BF16) return FNO_ERR_UNSUPPORTED;
+    if (C_in > 8 || C_out > 64) return FNO_ERR_UNSUPPORTED;
+    if (!al16(x) || !al16(w) || !al16(gy) || !al16(ws) || (b && !al16(b)) || (gw && !al16(gw)) || (gb && !al16(gb)))
+        return FNO_ERR_ALIGNMENT;
+    if (ws_bytes < glue_ws(C_in, 1, C_out)) return FNO_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = dtype == FNO_BF16
+                       ? launch_lift_bwd<__bf16>((const __bf16 *)x, (const __bf16 *)gy, w, b, (float *)ws, gw, gb, B,
+                                                 C_in, C_out, N, accumulate, st)
+                       : launch_lift_bwd<float>((const float *)x, (const float *)gy, w, b, (float *)ws, gw, gb, B, C_in,
+                                                C_out, N, accumulate, st);
+    return e == hipSuccess ? FNO_OK : FNO_ERR_HIP;
+}
+
+int fno_proj_fwd(int32_t dtype, int32_t B, int32_t C_in, int32_t H, int32_t C_out, int64_t N, const void *x,
+                 const float *w1, const float *b1, const float *w2, const float *b2, void *y, void *stream)
+{
+    if (B < 1 || C_in < 1 || H < 1 || C_out < 1 || N < 1 || !x || !w1 || !w2 || !y) return FNO_ERR_INVALID_ARG;
+    if (dtype != FNO_F32 && dtype != FNO_BF16) return FNO_ERR_UNSUPPORTED;
+    if (C_in > 32 || H > 128 || C_out != 1) return FNO_ERR_UNSUPPORTED;
+    if (!al16(x) || !al16(w1) || !al16(w2) || !al16(y) || (b1 && !al16(b1)) || (b2 && !al16(b2)))
+        return FNO_ERR_ALIGNMENT;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = dtype == FNO_BF16
+                       ? launch_proj<__bf16>(false, B, C_in, H, C_out, N, (const __bf16 *)x, nullptr, (__bf16 *)y, w1,
+                                             b1, w2, b2, nullptr, 0, st)
+                       : launch_proj<float>(false, B, C_in, H, C_out, N, (const float *)x, nullptr, (float *)y, w1, b1,
+                                            w2, b2, nullptr, 0, st);
+    return e == hipSuccess ? FNO_OK : FNO_ERR_HIP;
+}
+
+int fno_proj_bwd(int32_t dtype, int32_t B, int32_t C_in, int32_t H, int32_t C_out, int64_t N, const void *x,
+                 const float *w1, const float *b1, const float *w2, const float *b2, const void *gy, void *gx,
+                 float *gw1, float *gb1, float *gw2, float *gb2, int accumulate, void *ws, size_t ws_bytes,
+                 void *stream)
+{
+    (void)b2;
+    if (B < 1 || C_in < 1 || H < 1 || C_out < 1 || N < 1 || !x || !w1 || !w2 || !gy || !gx || !ws)
+        return FNO_ERR_INVALID_ARG;
+    if (dtype != FNO_F32 && dtype != FNO_BF16) return FNO_ERR_UNSUPPORTED;
+    if (C_in > 32 || H > 128 || C_out != 1) return FNO_ERR_UNSUPPORTED;
+    if (!al16(x) || !al16(w1) || !al16(w2) || !al16(gy) || !al16(gx) || !al16(ws) || (b1 && !al16(b1)) ||
+        (gw1 && !al16(gw1)) || (gb1 && !al16(gb1)) || (gw2 && !al16(gw2)) || (gb2 && !al16(gb2)))
+        return FNO_ERR_ALIGNMENT;
+    if (ws_bytes < glue_ws(C_in, H, C_out)) return FNO_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    float *part = (float *)ws;
+    hipError_t e = dtype == FNO_BF16
+                       ? launch_proj<__bf16>(true, B, C_in, H, C_out, N, (const __bf16 *)x, (const __bf16 *)gy,
+                                             (__bf16 *)gx, w1, b1, w2, b2, part, accumulate, st)
+                       : launch_proj<float>(true, B, C_in, H, C_out, N, (const float *)x, (const float *)gy,
+                                            (float *)gx, w1, b1, w2, b2, part, accumulate, st);
+    if (e != hipSuccess) return FNO_ERR_HIP;
+    const size_t row = proj_part_len(C_in, H);
+    const int nchunk = glue_blocks() * 4;
+    launch_sum_rows(part, gw1, H * C_in, row, nchunk, accumulate, st);
+    launch_sum_rows(part + (size_t)H * C_in, gb1, H, row, nchunk, accumulate, st);
+    launch_sum_rows(part + (size_t)H * C_in + H, gw2, H, row, nchunk, accumulate, st);
+    launch_sum_rows(part + (size_t)H * C_in + 2 * H, gb2, 1, row, nchunk, accumulate, st);
+    return hipGetLastError() == hipSuccess ? FNO_OK : FNO_ERR_HIP;
+}
+
+int fno_mse(int32_t dtype, int64_t n, const void *y, const void *target, float *loss, void *gy, void *ws,
+            size_t ws_bytes, void *stream)
+{
+    if (n < 1 || !y || !target || !loss || !ws) return FNO_ERR_INVALID_ARG;
+    if (dtype != FNO_F32 && dtype != FNO_BF16) return FNO_ERR_UNSUPPORTED;
+    if (!al16(y) || !al16(target) || !al16(ws) || (gy && !al16(gy))) return FNO_ERR_ALIGNMENT;
+    if (ws_bytes < (size_t)glue_blocks() * sizeof(float)) return FNO_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = dtype == FNO_BF16 ? launch_mse<__bf16>((const __bf16 *)y, (const __bf16 *)target, (__bf16 *)gy,
+                                                          (float *)ws, loss, n, st)
+                                     : launch_mse<float>((const float *)y, (const float *)target, (float *)gy,
+                                                         (float *)ws, loss, n, st);
+    return e == hipSuccess ? FNO_OK : FNO_ERR_HIP;
 }
 
 int fno_timing_enable(fno_plan_t *plan, int enable)

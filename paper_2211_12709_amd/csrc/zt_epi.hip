@@ -35,41 +35,6 @@ struct ZtArgs {
     int accumulate;
 };
 
-template <typename T> __device__ __forceinline__ typename OpOf<T>::type op_neg(typename OpOf<T>::type v);
-template <> __device__ __forceinline__ f4v op_neg<float>(f4v v) { return -v; }
-template <> __device__ __forceinline__ s4v op_neg<__bf16>(s4v v)
-{
-    return s4v{(short)(v[0] ^ (short)0x8000), (short)(v[1] ^ (short)0x8000), (short)(v[2] ^ (short)0x8000),
-               (short)(v[3] ^ (short)0x8000)};
-}
-
-template <typename T> __device__ __forceinline__ typename OpOf<T>::type op_from4(float a, float b, float c, float d);
-template <> __device__ __forceinline__ f4v op_from4<float>(float a, float b, float c, float d) { return f4v{a, b, c, d}; }
-template <> __device__ __forceinline__ s4v op_from4<__bf16>(float a, float b, float c, float d)
-{
-    return s4v{bf16_bits(a), bf16_bits(b), bf16_bits(c), bf16_bits(d)};
-}
-
-// 4 consecutive activations as floats (vector load).
-__device__ __forceinline__ void load4(const float *p, float (&v)[4])
-{
-    const f4v t = *reinterpret_cast<const f4v *>(p);
-    v[0] = t[0]; v[1] = t[1]; v[2] = t[2]; v[3] = t[3];
-}
-__device__ __forceinline__ void load4(const __bf16 *p, float (&v)[4])
-{
-    const s4v t = *reinterpret_cast<const s4v *>(p);
-    v[0] = op_get(t, 0); v[1] = op_get(t, 1); v[2] = op_get(t, 2); v[3] = op_get(t, 3);
-}
-__device__ __forceinline__ void store4(float *p, const float (&v)[4])
-{
-    *reinterpret_cast<f4v *>(p) = f4v{v[0], v[1], v[2], v[3]};
-}
-__device__ __forceinline__ void store4(__bf16 *p, const float (&v)[4])
-{
-    *reinterpret_cast<s4v *>(p) = s4v{bf16_bits(v[0]), bf16_bits(v[1]), bf16_bits(v[2]), bf16_bits(v[3])};
-}
-
 // NTT: (re/im, kt) tiles (1: Kt <= 8, 2: Kt <= 16).  MAXC: channel tiles (channels <= 16 MAXC).
 template <typename T, int EPI, int NTT, bool SPLIT, int MAXC>
 __global__ void __launch_bounds__(256) k_zt_epi(const float2 *__restrict__ u, T *__restrict__ out,

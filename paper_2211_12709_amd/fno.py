@@ -24,7 +24,8 @@ FNO_F32, FNO_BF16 = 0, 1
 OP_SPECTRAL_FWD, OP_SPECTRAL_BWD, OP_BLOCK_FWD, OP_BLOCK_BWD = range(4)
 
 EXPORTS = ("fno_desc_validate", "fno_plan_create", "fno_plan_destroy", "fno_workspace_bytes", "fno_cache_bytes",
-           "fno_spectral_fwd", "fno_spectral_bwd", "fno_block_fwd", "fno_block_bwd", "fno_timing_enable",
+           "fno_spectral_fwd", "fno_spectral_bwd", "fno_block_fwd", "fno_block_bwd", "fno_lift_fwd", "fno_lift_bwd",
+           "fno_proj_fwd", "fno_proj_bwd", "fno_mse", "fno_glue_workspace_bytes", "fno_timing_enable",
            "fno_timing_read", "fno_status_str")
 
 
@@ -62,6 +63,14 @@ def load_library(path: str = LIB_PATH):
     L.fno_spectral_bwd.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _sz, _vp]
     L.fno_block_fwd.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
     L.fno_block_bwd.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _sz, _vp]
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    L.fno_lift_fwd.argtypes = [i32, i32, i32, i32, i64, _vp, _vp, _vp, _vp, _vp]
+    L.fno_lift_bwd.argtypes = [i32, i32, i32, i32, i64, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _sz, _vp]
+    L.fno_proj_fwd.argtypes = [i32, i32, i32, i32, i32, i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    L.fno_proj_bwd.argtypes = [i32, i32, i32, i32, i32, i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                               ctypes.c_int, _vp, _sz, _vp]
+    L.fno_mse.argtypes = [i32, i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+    L.fno_glue_workspace_bytes.argtypes = [i32, i32, i32, ctypes.POINTER(_sz)]
     L.fno_timing_enable.argtypes = [_vp, ctypes.c_int]
     L.fno_timing_read.argtypes = [_vp, ctypes.c_char_p, _sz]
     L.fno_status_str.argtypes = [ctypes.c_int]
@@ -260,3 +269,161 @@ class FNOBlockFn(torch.autograd.Function):
                                           need_gw_pw=ctx.needs_input_grad[2],
                                           need_gb=ctx.has_bias and ctx.needs_input_grad[3])
         return gx, gw, gwpw, (gb if ctx.has_bias else None), None
+
+
+# ---------------------------------------------------------------------------
+# Network glue of Alg. 1: encoder (lifting), decoder (projection), MSE loss.
+_DTYPE_CODE = {torch.float32: FNO_F32, torch.bfloat16: FNO_BF16}
+_glue_ws = {}
+
+
+def _glue_workspace(device, ci, h, co):
+    n = _sz()
+    _check(load_library().fno_glue_workspace_bytes(ci, h, co, ctypes.byref(n)), "fno_glue_workspace_bytes")
+    key = (device, n.value)
+    ws = _glue_ws.get(device)
+    if ws is None or ws.numel() < n.value:
+        ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=device)
+        _glue_ws[device] = ws
+    return ws
+
+
+def _npts(t):
+    n = 1
+    for s in t.shape[2:]:
+        n *= s
+    return n
+
+
+def lift_fwd(x, w, b):
+    B, ci = x.shape[:2]
+    co = w.shape[0]
+    y = torch.empty((B, co, *x.shape[2:]), dtype=x.dtype, device=x.device)
+    _check(load_library().fno_lift_fwd(_DTYPE_CODE[x.dtype], B, ci, co, _npts(x), _ptr(x), _ptr(w), _ptr(b), _ptr(y),
+                                       _stream()), "fno_lift_fwd")
+    return y
+
+
+def lift_bwd(x, w, b, gy, need_gw=True, need_gb=True):
+    B, ci = x.shape[:2]
+    co = w.shape[0]
+    gw = torch.empty_like(w) if need_gw else None
+    gb = torch.empty((co,), dtype=torch.float32, device=x.device) if need_gb else None
+    ws = _glue_workspace(x.device, ci, 1, co)
+    _check(load_library().fno_lift_bwd(_DTYPE_CODE[x.dtype], B, ci, co, _npts(x), _ptr(x), _ptr(w), _ptr(b),
+                                       _ptr(gy), _ptr(gw), _ptr(gb), 0, _ptr(ws), ws.numel(), _stream()),
+           "fno_lift_bwd")
+    return gw, gb
+
+
+def proj_fwd(x, w1, b1, w2, b2):
+    B, ci = x.shape[:2]
+    h, co = w1.shape[0], w2.shape[0]
+    y = torch.empty((B, co, *x.shape[2:]), dtype=x.dtype, device=x.device)
+    _check(load_library().fno_proj_fwd(_DTYPE_CODE[x.dtype], B, ci, h, co, _npts(x), _ptr(x), _ptr(w1), _ptr(b1),
+                                       _ptr(w2), _ptr(b2), _ptr(y), _stream()), "fno_proj_fwd")
+    return y
+
+
+def proj_bwd(x, w1, b1, w2, b2, gy):
+    B, ci = x.shape[:2]
+    h, co = w1.shape[0], w2.shape[0]
+    gx = torch.empty_like(x)
+    gw1, gw2 = torch.empty_like(w1), torch.empty_like(w2)
+    gb1 = torch.empty((h,), dtype=torch.float32, device=x.device)
+    gb2 = torch.empty((co,), dtype=torch.float32, device=x.device)
+    ws = _glue_workspace(x.device, ci, h, co)
+    _check(load_library().fno_proj_bwd(_DTYPE_CODE[x.dtype], B, ci, h, co, _npts(x), _ptr(x), _ptr(w1), _ptr(b1),
+                                       _ptr(w2), _ptr(b2), _ptr(gy), _ptr(gx), _ptr(gw1), _ptr(gb1), _ptr(gw2),
+                                       _ptr(gb2), 0, _ptr(ws), ws.numel(), _stream()), "fno_proj_bwd")
+    return gx, gw1, gb1, gw2, gb2
+
+
+def mse(y, target, need_grad=True):
+    loss = torch.empty((1,), dtype=torch.float32, device=y.device)
+    gy = torch.empty_like(y) if need_grad else None
+    ws = _glue_workspace(y.device, 1, 1, 1)
+    _check(load_library().fno_mse(_DTYPE_CODE[y.dtype], y.numel(), _ptr(y), _ptr(target), _ptr(loss), _ptr(gy),
+                                  _ptr(ws), ws.numel(), _stream()), "fno_mse")
+    return loss, gy
+
+
+class LiftFn(torch.autograd.Function):
+    """Encoder of Alg. 1: GELU(w x + b) pointwise; no gradient to the (data) input."""
+
+    @staticmethod
+    def forward(ctx, x, w, b):
+        x, w, b = _c(x), _c(w), _c(b)
+        ctx.save_for_backward(x, w, b)
+        return lift_fwd(x, w, b)
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, w, b = ctx.saved_tensors
+        gw, gb = lift_bwd(x, w, b, _c(gy.to(x.dtype)))
+        return None, gw, gb
+
+
+class ProjFn(torch.autograd.Function):
+    """Decoder of Alg. 1: w2 GELU(w1 x + b1) + b2 pointwise (hidden layer never stored)."""
+
+    @staticmethod
+    def forward(ctx, x, w1, b1, w2, b2):
+        x, w1, b1, w2, b2 = (_c(t) for t in (x, w1, b1, w2, b2))
+        ctx.save_for_backward(x, w1, b1, w2, b2)
+        return proj_fwd(x, w1, b1, w2, b2)
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, w1, b1, w2, b2 = ctx.saved_tensors
+        gx, gw1, gb1, gw2, gb2 = proj_bwd(x, w1, b1, w2, b2, _c(gy.to(x.dtype)))
+        return gx, gw1, gb1, gw2, gb2
+
+
+class MseFn(torch.autograd.Function):
+    """Mean-squared error; returns a float32 scalar tensor."""
+
+    @staticmethod
+    def forward(ctx, y, target):
+        y, target = _c(y), _c(target.to(y.dtype))
+        loss, gy = mse(y, target, need_grad=True)
+        ctx.save_for_backward(gy)
+        return loss.reshape(())
+
+    @staticmethod
+    def backward(ctx, gl):
+        (gy,) = ctx.saved_tensors
+        return gy * gl.to(gy.dtype), None
+
+
+class FNO4d:
+    """The model-parallel FNO of Alg. 1 on one GPU: encoder (lifting 1x1 + GELU),
+    `nblocks` FNO blocks (spectral convolution + 1x1 + GELU, with per-block
+    recomputation in the backward), decoder (1x1 -> GELU -> 1x1).
+
+    Parameters are float32 tensors with requires_grad; activations use `dtype`
+    (torch.float32 or torch.bfloat16)."""
+
+    def __init__(self, in_ch, width, grid, modes, nblocks=4, hidden=128, out_ch=1, batch=1,
+                 dtype=torch.float32, params=None, device=None):
+        self.device = device or torch.device("cuda", torch.cuda.current_device())
+        self.dtype = dtype
+        self.plan = Plan(batch, width, width, grid, modes, FNO_BF16 if dtype == torch.bfloat16 else FNO_F32)
+        t = lambda a: torch.as_tensor(a).to(self.device).contiguous().requires_grad_(True)
+        if params is None:
+            raise ValueError("pass params = {'lift': (we, be), 'blocks': [(w, wpw, bpw), ...], 'proj': (w1, b1, w2, b2)}")
+        self.lift = [t(a) for a in params["lift"]]
+        self.blocks = [[t(a) for a in blk] for blk in params["blocks"]]
+        self.proj = [t(a) for a in params["proj"]]
+
+    def parameters(self):
+        out = list(self.lift)
+        for blk in self.blocks:
+            out += blk
+        return out + list(self.proj)
+
+    def __call__(self, x):
+        h = LiftFn.apply(x.to(self.dtype), *self.lift)
+        for (w, wpw, bpw) in self.blocks:
+            h = FNOBlockFn.apply(h, w, wpw, bpw, self.plan)
+        return ProjFn.apply(h, *self.proj)

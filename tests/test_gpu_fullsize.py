@@ -1,0 +1,101 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (same plans, same kernels):
+
+* the Navier-Stokes-shaped block (64^3 x 16, width 20, modes 12,12,12,8)
+  fwd + bwd against the full FP64 oracle (every output element);
+* the CO2-shaped block (128^3 x 32, width 20, modes 16,16,16,8): sampled
+  retained modes of the forward spectrum against the oracle's direct 4-D sums,
+  sampled output points of the spectral layer against the oracle's direct
+  synthesis from those modes being the only nonzero ones, and the adjoint
+  identity <S u, v> = <u, S* v> over the whole grid.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from paper_2211_12709_amd import inputs  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def fno():
+    from paper_2211_12709_amd import fno as f
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    f.load_library()
+    return f
+
+
+@pytest.fixture(scope="module")
+def o():
+    from oracle import oracle as orc
+    orc.lib()
+    return orc
+
+
+def rel(a, ref):
+    return float(np.linalg.norm((np.asarray(a) - ref).ravel()) / max(np.linalg.norm(np.ravel(ref)), 1e-300))
+
+
+def np64(t):
+    t = t.detach().cpu()
+    return t.numpy().astype(np.complex128) if t.is_complex() else t.float().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("code,tol", [(0, 1e-5), (1, 1e-2)], ids=["f32", "bf16"])
+def test_ns_block_full_size(fno, o, code, tol):
+    B, C, grid, modes = 1, 20, (64, 64, 64, 16), (12, 12, 12, 8)
+    d = o.Dims(B, C, C, grid, modes)
+    print(f"ns block 64^3x16 dtype={code}", flush=True)
+    x = inputs.smooth_spacetime_field(B, C, grid, seed=inputs.SEED_INPUT, corr_len=8.0)
+    gy = inputs.smooth_spacetime_field(B, C, grid, seed=inputs.SEED_TARGET, corr_len=8.0)
+    w, wpw, bpw = inputs.block_params(C, C, d.kshape, block=0)
+    plan = fno.Plan(B, C, C, grid, modes, code)
+    xq = torch.from_numpy(x).cuda().to(plan.act_dtype)
+    gyq = torch.from_numpy(gy).cuda().to(plan.act_dtype)
+    tw, twp, tb = (torch.from_numpy(a).cuda() for a in (w, wpw, bpw))
+    cache = plan.new_cache()
+    y = plan.block_fwd(xq, tw, twp, tb, cache=cache)
+    gx, gw, gwpw, gb = plan.block_bwd(xq, cache, tw, twp, tb, gyq)
+    torch.cuda.synchronize()
+    y_ref = o.block_fwd(d, x, w, wpw, bpw)
+    e_y = rel(np64(y), y_ref)
+    del y_ref
+    gx_ref, gw_ref, gwpw_ref, gb_ref = o.block_bwd(d, x, w, wpw, bpw, gy)
+    errs = dict(y=e_y, gx=rel(np64(gx), gx_ref), gw=rel(np64(gw), gw_ref), gw_pw=rel(np64(gwpw), gwpw_ref),
+                gb=rel(np64(gb), gb_ref))
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v < tol, (k, v)
+
+
+def test_co2_block_sampled_modes_and_adjoint(fno, o):
+    B, C, grid, modes = 1, 20, (128, 128, 128, 32), (16, 16, 16, 8)
+    d = o.Dims(B, C, C, grid, modes)
+    print("co2 128^3x32 sampled", flush=True)
+    x = inputs.smooth_spacetime_field(B, C, grid, seed=inputs.SEED_INPUT)
+    w = inputs.spectral_weights(C, C, d.kshape, seed=inputs.SEED_SPECTRAL_W)
+    plan = fno.Plan(B, C, C, grid, modes, 0)
+    xq = torch.from_numpy(x).cuda()
+    cache = plan.new_cache()
+    tw = torch.from_numpy(w).cuda()
+    y = plan.spectral_fwd(xq, tw, cache=cache)
+    torch.cuda.synchronize()
+    nxh = B * C * d.nmode
+    xh = cache[: nxh * 8].view(torch.complex64).reshape(B, C, *d.kshape)
+    # sampled retained modes: the lowest, both Nyquist-side corners, and interior ones
+    kidx = np.array([[0, 0, 0, 0], [31, 31, 31, 7], [16, 3, 30, 1], [5, 17, 9, 4]], dtype=np.int32)
+    ref = o.dft_modes(d, x[:, :4], kidx)   # 4 channels keep the direct sums short
+    got = np64(xh)[:, :4][:, :, kidx[:, 0], kidx[:, 1], kidx[:, 2], kidx[:, 3]]
+    e_modes = rel(got, ref)
+    print(f"sampled X^ rel {e_modes:.2e}", flush=True)
+    assert e_modes < 1e-5
+    # adjoint identity over the whole grid with the spectral layer's own backward
+    v = torch.from_numpy(inputs.smooth_spacetime_field(B, C, grid, seed=77)).cuda()
+    gx, _ = plan.spectral_bwd(v, tw, need_gw=False)
+    lhs = float((y.double() * v.double()).sum())
+    rhs = float((xq.double() * gx.double()).sum())
+    print(f"<Su,v>={lhs:.6e} <u,S*v>={rhs:.6e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-5 * (abs(lhs) + abs(rhs))
