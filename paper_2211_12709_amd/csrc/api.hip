@@ -52,7 +52,8 @@ int zt_grid(const Dims &d);
 template <typename T>
 hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const float2 *u, T *out, const T *src, const T *gy,
                      const float *wpw, const float *bpw, float *part, const ZtTabs &tb, int accumulate, hipStream_t st,
-                     int *grid_used = nullptr);
+                     int *rows_used = nullptr);
+int zt_partial_rows(const Dims &d);
 template <typename TC>
 hipError_t launch_axis_mfma(const float2 *in, float2 *out, const void *tab, const void *tab_lo, long long outer,
                             int Nin, int Nout, long long cols, hipStream_t st);
@@ -173,7 +174,7 @@ static WsPlan ws_plan(const Dims &d, int op)
     w.sp3 = take(sizeof(float2) * (size_t)(d.B * C * d.nmode));
     if (op == FNO_OP_BLOCK_BWD) {
         w.gz = take(sizeof(float) * (size_t)(d.B * d.Co * d.ncell));
-        const size_t chunks = std::max<size_t>(pw_wgrad_chunks(d.B * d.ncell), (size_t)zt_grid(d) * 4);
+        const size_t chunks = std::max<size_t>(pw_wgrad_chunks(d.B * d.ncell), (size_t)zt_partial_rows(d));
         w.part = take(sizeof(float) * chunks * d.Co * (d.Ci + 1));
     }
     w.total = off;
@@ -197,9 +198,20 @@ static int check_plan(const fno_plan_t *plan)
     return FNO_OK;
 }
 
+// First launch error of the current entry point on this host thread (launchers
+// that return hipError_t report through it; finish() reports and clears it).
+static thread_local hipError_t g_launch_err = hipSuccess;
+static void note(hipError_t e)
+{
+    if (e != hipSuccess && g_launch_err == hipSuccess) g_launch_err = e;
+}
+
 static int finish()
 {
-    return hipGetLastError() == hipSuccess ? FNO_OK : FNO_ERR_HIP;
+    const hipError_t e = g_launch_err;
+    g_launch_err = hipSuccess;
+    const hipError_t last = hipGetLastError();
+    return (e == hipSuccess && last == hipSuccess) ? FNO_OK : FNO_ERR_HIP;
 }
 
 // X^ of activations `in` (C channels) into xh, using t1/t2 as scratch.
@@ -212,7 +224,7 @@ static void axis_stage(const fno_plan_t *p, int ax, bool forward, const float2 *
     const int Nin = forward ? d.N[ax] : d.K[ax], Nout = forward ? d.K[ax] : d.N[ax];
     const Tables::Frag &tb = forward ? p->tab.ax_fwd[ax] : p->tab.ax_inv[ax];
     if (axis_lds_bytes((Nin + 15) / 16 * 16, 4) <= 160 * 1024) {
-        FNO_TIMED(p, st, name, (void)launch_axis_mfma<float>(in, out, tb.f, nullptr, outer, Nin, Nout, cols, st));
+        FNO_TIMED(p, st, name, note(launch_axis_mfma<float>(in, out, tb.f, nullptr, outer, Nin, Nout, cols, st)));
     } else {
         FNO_TIMED(p, st, name, launch_axis(in, out, p->tab.cs[ax], outer, Nin, Nout, cols, d.N[ax], forward ? 0 : 1, st));
     }
@@ -241,7 +253,7 @@ static void forward_spectrum(const fno_plan_t *p, const T *in, int C, const floa
     const Dims &d = p->d;
     if (tzy_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
         FNO_TIMED(p, st, sizeof(T) == 2 ? "tzy_fwd<bf16>" : "tzy_fwd<f32>",
-                  (void)launch_tzy<T>(in, t2, (long long)d.B * C * d.N[0], tzy_tabs<T>(p, wt), d, st));
+                  note(launch_tzy<T>(in, t2, (long long)d.B * C * d.N[0], tzy_tabs<T>(p, wt), d, st)));
     } else {
         FNO_TIMED(p, st, sizeof(T) == 2 ? "fwd_tz<bf16>" : "fwd_tz<f32>",
                   launch_fwd_tz<T>(in, t1, (long long)d.B * C * d.N[0] * d.N[1], d, p->tab, wt, st));
@@ -292,9 +304,9 @@ static int spectral_or_block_fwd(const fno_plan_t *p, const void *x_, const void
     inverse_xy(p, yh, d.Co, u2, t1, st);
     if (zt_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
         FNO_TIMED(p, st, block ? "zt_block" : "zt_plain",
-                  (void)launch_zt<T>(block ? ZEPI_BLOCK : ZEPI_PLAIN, d, d.Co, block ? d.Ci : 0, t1, (T *)y_, x,
+                  note(launch_zt<T>(block ? ZEPI_BLOCK : ZEPI_PLAIN, d, d.Co, block ? d.Ci : 0, t1, (T *)y_, x,
                                      nullptr, (const float *)wpw, (const float *)bpw, nullptr, zt_tabs<T>(p, false), 0,
-                                     st));
+                                     st)));
     } else {
         FNO_TIMED(p, st, block ? "inv_zt_block" : "inv_zt_plain",
                   launch_inv_zt<T>(block ? EPI_BLOCK : EPI_PLAIN, t1, (T *)y_, d.Co, d, p->tab, p->tab.wt_inv, x,
@@ -338,8 +350,8 @@ static int spectral_bwd_impl(const fno_plan_t *p, const void *x_, const void *ca
         inverse_xy(p, gxh, d.Ci, t2, t1, st);
         if (zt_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
             FNO_TIMED(p, st, "zt_adj",
-                      (void)launch_zt<T>(ZEPI_ADJ, d, d.Ci, 0, t1, (T *)gx_, nullptr, nullptr, nullptr, nullptr,
-                                         nullptr, zt_tabs<T>(p, true), accumulate, st));
+                      note(launch_zt<T>(ZEPI_ADJ, d, d.Ci, 0, t1, (T *)gx_, nullptr, nullptr, nullptr, nullptr,
+                                         nullptr, zt_tabs<T>(p, true), accumulate, st)));
         } else {
             FNO_TIMED(p, st, "inv_zt_adj",
                       launch_inv_zt<T>(EPI_ADJ, t1, (T *)gx_, d.Ci, d, p->tab, p->tab.wt_one, nullptr, nullptr,
@@ -375,21 +387,21 @@ static int block_bwd_impl(const fno_plan_t *p, const void *x_, const void *cache
     inverse_xy(p, nullptr, d.Co, const_cast<float2 *>(u2), t1, st, true);
     if (zt_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
         T *gzt = (T *)gz;  // gz stored in the activation type
-        int grid_used = zt_grid(d);
+        int rows_used = zt_partial_rows(d);
         FNO_TIMED(p, st, "zt_bwd",
-                  (void)launch_zt<T>(ZEPI_BWD, d, d.Co, d.Ci, t1, gzt, x, (const T *)gy_, wpw, bpw, part,
-                                     zt_tabs<T>(p, false), 0, st, &grid_used));
+                  note(launch_zt<T>(ZEPI_BWD, d, d.Co, d.Ci, t1, gzt, x, (const T *)gy_, wpw, bpw, part,
+                                     zt_tabs<T>(p, false), 0, st, &rows_used)));
         if (gwpw_ || gb_)
             FNO_TIMED(p, st, "pw_reduce",
-                      launch_pw_reduce(part, (float *)gwpw_, (float *)gb_, d.Ci, d.Co, grid_used * 4, accumulate, st));
+                      launch_pw_reduce(part, (float *)gwpw_, (float *)gb_, d.Ci, d.Co, rows_used, accumulate, st));
         forward_spectrum<T>(p, gzt, d.Co, p->tab.wt_inv, t1, t2, gyh, st);
         FNO_TIMED(p, st, "mix_bwd",
                   launch_mix_bwd(xh, (const float2 *)w_, gyh, gxh, (float2 *)gw_, d.B, d.Ci, d.Co, d.nmode, accumulate,
                                  st));
         inverse_xy(p, gxh, d.Ci, t2, t1, st);
         FNO_TIMED(p, st, "zt_adj",
-                  (void)launch_zt<T>(ZEPI_ADJ, d, d.Ci, d.Co, t1, (T *)gx_, gzt, nullptr, wpw, nullptr, nullptr,
-                                     zt_tabs<T>(p, true), accumulate, st));
+                  note(launch_zt<T>(ZEPI_ADJ, d, d.Ci, d.Co, t1, (T *)gx_, gzt, nullptr, wpw, nullptr, nullptr,
+                                     zt_tabs<T>(p, true), accumulate, st)));
         return finish();
     }
     FNO_TIMED(p, st, "bwd_gz", launch_bwd_gz<T>(t1, x, (const T *)gy_, gz, d, p->tab, wpw, bpw, st));

@@ -87,51 +87,67 @@ __global__ void __launch_bounds__(256) k_tzy_fwd(const T *__restrict__ x, float2
 
     const int nplanes = a.NYC * per_wave;  // plane slots of this wave
     auto plane_y = [&](int s) { return (s / per_wave) * a.Yc + (s % per_wave) * 4 + w; };
-    // one plane's t and z steps, staged into LDS (or zeros for a padding plane)
-    auto do_plane = [&](int s, const Op (&xa)[NZBM][2]) {
-        const int yl = (s % per_wave) * 4 + w;
-        const int y = plane_y(s);
+    // t and z steps of two planes (s, s + 1) at once: every z-basis fragment read
+    // from LDS feeds both planes, and the two independent MFMA chains overlap.
+    // Planes beyond Ny have zero input (guarded loads), hence a zero spectrum.
+    auto do_pair = [&](int s, const Op (&xa)[NZBM][2], const Op (&xb)[NZBM][2]) {
         // keep the LDS basis reads inside the plane loop (no hoisting into registers)
         asm volatile("" ::: "memory");
-        if (y < Ny) {
-            // Pc: cos rows (kz block kb), Ps: sin rows, both [kb][nt]
-            f4v Pc[MAXKB][NTT], Ps[MAXKB][NTT];
+        f4v Pc[2][MAXKB][NTT], Ps[2][MAXKB][NTT];  // [plane][kz block][n tile]: cos rows, sin rows
+#pragma unroll
+        for (int u = 0; u < 2; u++)
 #pragma unroll
             for (int kb = 0; kb < MAXKB; kb++)
 #pragma unroll
-                for (int nt = 0; nt < NTT; nt++) Pc[kb][nt] = Ps[kb][nt] = f4_zero();
+                for (int nt = 0; nt < NTT; nt++) Pc[u][kb][nt] = Ps[u][kb][nt] = f4_zero();
 #pragma unroll
-            for (int zb = 0; zb < NZBM; zb++) {
-                if (zb < a.NZB) {
-                    f4v c1[NTT];
+        for (int zb = 0; zb < NZBM; zb++) {
+            if (zb < a.NZB) {
+                Op bz[2][NTT];
 #pragma unroll
-                    for (int nt = 0; nt < NTT; nt++) {
-                        c1[nt] = f4_zero();
+                for (int nt = 0; nt < NTT; nt++) {
+                    f4v c0 = f4_zero(), c1 = f4_zero();
 #pragma unroll
-                        for (int q = 0; q < 2; q++)
-                            if (q < a.NQ) {
-                                c1[nt] = mma16(xa[zb][q], tb[q][nt], c1[nt]);
-                                if (SPLIT) c1[nt] = mma16(xa[zb][q], tbl[q][nt], c1[nt]);
+                    for (int q = 0; q < 2; q++)
+                        if (q < a.NQ) {
+                            c0 = mma16(xa[zb][q], tb[q][nt], c0);
+                            c1 = mma16(xb[zb][q], tb[q][nt], c1);
+                            if (SPLIT) {
+                                c0 = mma16(xa[zb][q], tbl[q][nt], c0);
+                                c1 = mma16(xb[zb][q], tbl[q][nt], c1);
                             }
-                    }
+                        }
+                    bz[0][nt] = to_op<T>(c0);
+                    bz[1][nt] = to_op<T>(c1);
+                }
 #pragma unroll
-                    for (int nt = 0; nt < NTT; nt++) {
-                        const Op bz = to_op<T>(c1[nt]);
+                for (int kb = 0; kb < MAXKB; kb++)
+                    if (kb < a.KB) {
+                        const int ic = (zb * a.MZ + kb) * 64 + lane, is = (zb * a.MZ + a.KB + kb) * 64 + lane;
+                        const Op zc = zl[ic], zs = zl[is];
+                        Op zcl, zsl;
+                        if (SPLIT) {
+                            zcl = zl[nzf + ic];
+                            zsl = zl[nzf + is];
+                        }
 #pragma unroll
-                        for (int kb = 0; kb < MAXKB; kb++)
-                            if (kb < a.KB) {
-                                const int ic = (zb * a.MZ + kb) * 64 + lane, is = (zb * a.MZ + a.KB + kb) * 64 + lane;
-                                Pc[kb][nt] = mma16(zl[ic], bz, Pc[kb][nt]);
-                                Ps[kb][nt] = mma16(zl[is], bz, Ps[kb][nt]);
+                        for (int u = 0; u < 2; u++)
+#pragma unroll
+                            for (int nt = 0; nt < NTT; nt++) {
+                                Pc[u][kb][nt] = mma16(zc, bz[u][nt], Pc[u][kb][nt]);
+                                Ps[u][kb][nt] = mma16(zs, bz[u][nt], Ps[u][kb][nt]);
                                 if (SPLIT) {
-                                    Pc[kb][nt] = mma16(zl[nzf + ic], bz, Pc[kb][nt]);
-                                    Ps[kb][nt] = mma16(zl[nzf + is], bz, Ps[kb][nt]);
+                                    Pc[u][kb][nt] = mma16(zcl, bz[u][nt], Pc[u][kb][nt]);
+                                    Ps[u][kb][nt] = mma16(zsl, bz[u][nt], Ps[u][kb][nt]);
                                 }
                             }
                     }
-                }
             }
-            // combine cos/sin halves into the complex spectrum and stage it in LDS
+        }
+        // combine cos/sin halves into the complex spectrum and stage it in LDS
+#pragma unroll
+        for (int u = 0; u < 2; u++) {
+            const int yl = ((s + u) % per_wave) * 4 + w;
 #pragma unroll
             for (int kb = 0; kb < MAXKB; kb++) {
                 if (kb < a.KB) {
@@ -141,13 +157,14 @@ __global__ void __launch_bounds__(256) k_tzy_fwd(const T *__restrict__ x, float2
                         if (NTT == 1) {
 #pragma unroll
                             for (int r = 0; r < 4; r++) {
-                                const float ps = row_ror8(Ps[kb][0][r]);
-                                v[r] = c < 8 ? Pc[kb][0][r] + ps : Pc[kb][0][r] - ps;
+                                const float ps = row_ror8(Ps[u][kb][0][r]);
+                                v[r] = c < 8 ? Pc[u][kb][0][r] + ps : Pc[u][kb][0][r] - ps;
                             }
                         } else {
 #pragma unroll
                             for (int r = 0; r < 4; r++)
-                                v[r] = nt == 0 ? Pc[kb][0][r] + Ps[kb][NTT - 1][r] : Pc[kb][NTT - 1][r] - Ps[kb][0][r];
+                                v[r] = nt == 0 ? Pc[u][kb][0][r] + Ps[u][kb][NTT - 1][r]
+                                               : Pc[u][kb][NTT - 1][r] - Ps[u][kb][0][r];
                         }
                         const int ri = NTT == 1 ? (c >> 3) : nt;
                         const int kt = NTT == 1 ? (c & 7) : c;
@@ -158,11 +175,6 @@ __global__ void __launch_bounds__(256) k_tzy_fwd(const T *__restrict__ x, float2
                         }
                     }
                 }
-            }
-        } else {
-            for (int col = lane; col < ncol; col += 64) {
-                tl[col * ldk + yl] = from_f32<T>(0.f);
-                tl[col * ldk + a.Yc + yl] = from_f32<T>(0.f);
             }
         }
     };
@@ -199,18 +211,19 @@ __global__ void __launch_bounds__(256) k_tzy_fwd(const T *__restrict__ x, float2
         }
     };
 
-    // rotating register buffers: DEPTH planes are in flight while one is processed
+    // rotating register buffers: DEPTH planes are in flight while a pair is processed
     constexpr int DEPTH = sizeof(T) == 2 ? 4 : 2;
     Op xb[DEPTH][NZBM][2];
 #pragma unroll
     for (int k = 0; k < DEPTH; k++) load_plane(plane_y(k), xb[k]);
     for (int s0 = 0; s0 < nplanes; s0 += DEPTH) {  // nplanes is a multiple of DEPTH
 #pragma unroll
-        for (int k = 0; k < DEPTH; k++) {
+        for (int k = 0; k < DEPTH; k += 2) {
             const int s = s0 + k;
-            do_plane(s, xb[k]);
-            chunk_end(s);
+            do_pair(s, xb[k], xb[k + 1]);
+            chunk_end(s + 1);
             if (s + DEPTH < nplanes) load_plane(plane_y(s + DEPTH), xb[k]);
+            if (s + 1 + DEPTH < nplanes) load_plane(plane_y(s + 1 + DEPTH), xb[k + 1]);
         }
     }
 
@@ -251,7 +264,7 @@ static hipError_t launch_tzy_t(const T *x, float2 *t2, long long slabs, const Tz
     typedef typename OpOf<T>::type Op;
     constexpr bool SPLIT = sizeof(T) == 2;  // bfloat16 kernels use the hi/lo basis
     const size_t lds = tzy_lds_bytes(a, sizeof(T), SPLIT);
-    auto kern = k_tzy_fwd<T, NTT, SPLIT, MY, NBW, 8, 4>;
+    auto kern = k_tzy_fwd<T, NTT, SPLIT, MY, NBW, 8, 2>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -272,10 +285,10 @@ static void tzy_tiles(const Dims &d, int &MY, int &NBW)
 bool tzy_supported(const Dims &d, int dtype)
 {
     const int Nt = d.N[3], Nz = d.N[2];
-    if (Nt % 4 != 0 || Nt > 32 || Nz > 128 || d.K[3] > 16 || d.K[2] > 64) return false;
+    if (Nt % 4 != 0 || Nt > 32 || Nz > 128 || d.K[3] > 16 || d.K[2] > 32) return false;
     int MY, NBW;
     tzy_tiles(d, MY, NBW);
-    if (MY > 8 || NBW > 8 || MY * NBW > 32 || (MY > 4 && NBW > 4)) return false;
+    if (MY > 4 || NBW > 8) return false;
     TzyArgs a{};
     a.NZB = (Nz + 15) / 16;
     a.MZ = 2 * ((d.K[2] + 15) / 16);
@@ -311,10 +324,8 @@ static hipError_t launch_tzy_n(const T *x, float2 *t2, long long slabs, const Tz
 {
     if (MY == 2) return NBW <= 4 ? launch_tzy_t<T, NTT, 2, 4>(x, t2, slabs, tb, a, st)
                                  : launch_tzy_t<T, NTT, 2, 8>(x, t2, slabs, tb, a, st);
-    if (MY == 4) return NBW <= 4 ? launch_tzy_t<T, NTT, 4, 4>(x, t2, slabs, tb, a, st)
-                                 : launch_tzy_t<T, NTT, 4, 8>(x, t2, slabs, tb, a, st);
-    if (MY == 6) return launch_tzy_t<T, NTT, 6, 4>(x, t2, slabs, tb, a, st);
-    return launch_tzy_t<T, NTT, 8, 4>(x, t2, slabs, tb, a, st);
+    return NBW <= 4 ? launch_tzy_t<T, NTT, 4, 4>(x, t2, slabs, tb, a, st)
+                    : launch_tzy_t<T, NTT, 4, 8>(x, t2, slabs, tb, a, st);
 }
 
 template <typename T>

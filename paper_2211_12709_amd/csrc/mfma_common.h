@@ -89,6 +89,10 @@ template <> __device__ __forceinline__ s4v op_from4<__bf16>(float a, float b, fl
     return s4v{bf16_bits(a), bf16_bits(b), bf16_bits(c), bf16_bits(d)};
 }
 
+// Store element j of a fragment to *p (its storage type, bits unchanged).
+__device__ __forceinline__ void op_put(float *p, f4v v, int j) { *p = v[j]; }
+__device__ __forceinline__ void op_put(__bf16 *p, s4v v, int j) { *reinterpret_cast<short *>(p) = v[j]; }
+
 // 4 consecutive activations as floats (vector load).
 __device__ __forceinline__ void load4(const float *p, float (&v)[4])
 {

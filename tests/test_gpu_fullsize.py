@@ -4,10 +4,11 @@ times (same plans, same kernels):
 * the Navier-Stokes-shaped block (64^3 x 16, width 20, modes 12,12,12,8)
   fwd + bwd against the full FP64 oracle (every output element);
 * the CO2-shaped block (128^3 x 32, width 20, modes 16,16,16,8): sampled
-  retained modes of the forward spectrum against the oracle's direct 4-D sums,
-  sampled output points of the spectral layer against the oracle's direct
-  synthesis from those modes being the only nonzero ones, and the adjoint
-  identity <S u, v> = <u, S* v> over the whole grid.
+  retained modes of the forward spectrum against the oracle's direct 4-D sums
+  and the adjoint identity <S u, v> = <u, S* v> over the whole grid.  The
+  input there is white noise, so every retained mode carries energy of the
+  same order; a smooth field's highest retained modes sit at the rounding
+  level of the FP32 transform and make a relative comparison meaningless.
 """
 import numpy as np
 import pytest
@@ -75,7 +76,7 @@ def test_co2_block_sampled_modes_and_adjoint(fno, o):
     B, C, grid, modes = 1, 20, (128, 128, 128, 32), (16, 16, 16, 8)
     d = o.Dims(B, C, C, grid, modes)
     print("co2 128^3x32 sampled", flush=True)
-    x = inputs.smooth_spacetime_field(B, C, grid, seed=inputs.SEED_INPUT)
+    x = inputs.normal_field((B, C, *grid), seed=inputs.SEED_INPUT)
     w = inputs.spectral_weights(C, C, d.kshape, seed=inputs.SEED_SPECTRAL_W)
     plan = fno.Plan(B, C, C, grid, modes, 0)
     xq = torch.from_numpy(x).cuda()
@@ -92,8 +93,11 @@ def test_co2_block_sampled_modes_and_adjoint(fno, o):
     e_modes = rel(got, ref)
     print(f"sampled X^ rel {e_modes:.2e}", flush=True)
     assert e_modes < 1e-5
-    # adjoint identity over the whole grid with the spectral layer's own backward
-    v = torch.from_numpy(inputs.smooth_spacetime_field(B, C, grid, seed=77)).cuda()
+    # adjoint identity over the whole grid with the spectral layer's own backward; v leans on
+    # S u so that <S u, v> is of the order of ||S u||^2 and a relative bound is meaningful
+    noise = torch.from_numpy(inputs.normal_field((B, C, *grid), seed=77)).cuda()
+    v = y + 0.5 * float(y.double().pow(2).mean().sqrt()) * noise
+    del noise
     gx, _ = plan.spectral_bwd(v, tw, need_gw=False)
     lhs = float((y.double() * v.double()).sum())
     rhs = float((xq.double() * gx.double()).sum())
