@@ -11,22 +11,29 @@
 //
 // Per plane (one workgroup of NW waves), for each chunk of 16 values of z:
 //   phase 1  V^T_c[(re/im, kt)][z] = Au_c[(re/im, kt)][(re/im', kz)] Ez[(re/im', kz)][z]   for every channel c
-//            (Au holds [[Ur, -Ui], [Ui, Ur]], Ez [cos; sin]) -> LDS as V[z][c][(re/im, kt)]
+//            (Au holds [[Ur, -Ui], [Ui, Ur]], Ez [cos; sin]) -> LDS as V[z][c][(re/im, kt)].
+//            U is staged as [c][kz / 4][kt][kz % 4] so the 16 rows (re/im, kt) of an operand
+//            fragment fall in distinct banks.
 //   phase 2  output columns are (z, channel) pairs, z major: a group of ZG consecutive z holds
 //            ZG Cs columns, a multiple of 16, so no matrix-core column is padding whatever the
 //            channel count.  For one 16-column tile:
 //              Out^T[t][(z, co)] = Tb^T[t][k] V[k][(z, co)] + sum_(z', ci) xT[t][(z', ci)] Wd[(z', ci)][(z, co)]
 //            with Wd[(z', ci)][(z, co)] = W[co][ci] if z' = z else 0 (block diagonal over z): the
 //            synthesis and the pointwise 1x1 land in one accumulator, four consecutive t per lane.
-//            (group, tile) pairs are spread over the waves; per-tile column maps live in LDS.
-//   EPI_BWD  after the chunk, per z: gW^T[i][o] += sum_t x[i][t] gz[o][t] from the chunk's
-//            source and gradient, read back in their natural [c][z][t] layout.
+//            Wave w always computes tile j = w mod NT (of groups w / NT, w / NT + R, ...), so its
+//            column map, pointwise-weight fragments and EPI_BWD accumulators stay in registers.
+//   EPI_BWD  the gradient tile is then the B operand of
+//              C[(z', i)][(z, o)] += sum_t x[z'][i][t] gz[z][o][t];
+//            its z' = z entries, summed over z, are the pointwise-weight gradient.
 #include "fno_internal.h"
 #include "mfma_common.h"
 
 namespace fno {
 
 enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3 };
+
+constexpr int kZtMaxWaves = 16;
+constexpr int kZtMaxSpan = 4;
 
 struct ZtArgs {
     int B, Nx, Ny, Nz, Nt, Kz, Kt, Kzp;
@@ -37,10 +44,11 @@ struct ZtArgs {
     int NTQ;   // t tiles: ceil(Nt / 16)
     int ZG;    // z values per column group: 16 / gcd(Cs, 16)
     int NT;    // 16-column tiles per group: ZG Cs / 16
-    int SPAN;  // most 16-deep source K chunks one tile covers
+    int R;     // waves per tile index: NW = NT R
+    int SPAN;  // source K chunks per tile (2 or 4; 1 with no source)
     int ldT;   // row stride (elements) of the transposed source chunk [t][(z, ci)]
-    // LDS byte offsets
-    int off_v, off_x, off_wd, off_tcol, off_tzr, off_tb, off_tq;
+    int uim_off;       // element offset of the U imaginary plane (its bank offset is 16 words)
+    int off_v, off_x;  // LDS byte offsets of the V chunk and the transposed source chunk
     int accumulate;
 };
 
@@ -52,98 +60,96 @@ __device__ __forceinline__ s4v op_sign(s4v v, bool neg)
     return s4v{(short)(v[0] ^ m), (short)(v[1] ^ m), (short)(v[2] ^ m), (short)(v[3] ^ m)};
 }
 
-// NTT: (re/im, kt) tiles (1: Kt <= 8, 2: Kt <= 16).  NW: waves per workgroup.
-// MAXC: 16-channel tiles of the BWD weight-gradient product (channels <= 16 MAXC).
-template <typename T, int EPI, int NTT, bool SPLIT, int NW, int MAXC>
-__global__ void __launch_bounds__(64 * NW) k_zt_epi(const float2 *__restrict__ u, T *__restrict__ out,
-                                                    const T *__restrict__ src, const T *__restrict__ gy,
-                                                    const float *__restrict__ wpw, const float *__restrict__ bpw,
-                                                    float *__restrict__ part,
-                                                    const typename OpOf<T>::type *__restrict__ tabZ,
-                                                    const typename OpOf<T>::type *__restrict__ tabZ_lo,
-                                                    const typename OpOf<T>::type *__restrict__ tabT,
-                                                    const typename OpOf<T>::type *__restrict__ tabT_lo, ZtArgs a)
+// Operand fragment from four scalars of storage type T, `stride` elements apart (bits unchanged).
+__device__ __forceinline__ f4v op_gather(const float *p, int stride)
+{
+    return f4v{p[0], p[stride], p[2 * stride], p[3 * stride]};
+}
+__device__ __forceinline__ s4v op_gather(const __bf16 *p, int stride)
+{
+    const short *q = reinterpret_cast<const short *>(p);
+    return s4v{q[0], q[stride], q[2 * stride], q[3 * stride]};
+}
+
+template <int EPI> constexpr bool has_src_c() { return EPI != ZEPI_PLAIN; }
+
+// NTT: (re/im, kt) tiles (1: Kt <= 8, 2: Kt <= 16).  NTQ: t tiles (1: Nt <= 16, 2: Nt <= 32).
+// SPAN: source K chunks every tile multiplies (weight fragments beyond a tile's own chunks are zero).
+// The workgroup has NW = NT R waves (<= MAXW).
+template <typename T, int EPI, int NTT, int NTQ, int SPAN, bool SPLIT, int MAXW>
+__global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : (EPI == ZEPI_BWD ? 4 : 5)))) k_zt_epi(const float2 *__restrict__ u, T *__restrict__ out,
+                                                             const T *__restrict__ src, const T *__restrict__ gy,
+                                                             const float *__restrict__ wpw,
+                                                             const float *__restrict__ bpw, float *__restrict__ part,
+                                                             const typename OpOf<T>::type *__restrict__ tabZ,
+                                                             const typename OpOf<T>::type *__restrict__ tabZ_lo,
+                                                             const typename OpOf<T>::type *__restrict__ tabT,
+                                                             const typename OpOf<T>::type *__restrict__ tabT_lo,
+                                                             ZtArgs a)
 {
     typedef typename OpOf<T>::type Op;
     constexpr bool PW = EPI != ZEPI_PLAIN;
     constexpr int ZC = 16;  // z values per chunk
-    constexpr int NTH = 64 * NW;
     extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int NTH = blockDim.x, NW = NTH >> 6;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
     const int Nz = a.Nz, Nt = a.Nt, Kt = a.Kt, Kzp = a.Kzp, Cs = a.Cs, Csrc = a.Csrc, Csp = a.Csp;
-    const int ZG = a.ZG, NT = a.NT, ldT = a.ldT, KK = a.Kz * Kt;
+    const int ZG = a.ZG, NT = a.NT, R = a.R, ldT = a.ldT, KK = a.Kz * Kt;
+    const bool has_src = PW && Csrc > 0;
     const long long nxy = (long long)a.Nx * a.Ny, plane = (long long)Nz * Nt, ncell = nxy * plane;
 
     const int ldv = 16 * NTT + 4;
     T *ure = reinterpret_cast<T *>(smem);
-    T *uim = ure + (size_t)Cs * Kt * Kzp;
+    T *uim = ure + a.uim_off;
     T *vl = reinterpret_cast<T *>(smem + a.off_v);
     T *xt = reinterpret_cast<T *>(smem + a.off_x);
-    Op *wdl = reinterpret_cast<Op *>(smem + a.off_wd);
-    long long *tcol = reinterpret_cast<long long *>(smem + a.off_tcol);
-    int *tzr = reinterpret_cast<int *>(smem + a.off_tzr);
-    float *tb = reinterpret_cast<float *>(smem + a.off_tb);
-    int *tq = reinterpret_cast<int *>(smem + a.off_tq);
 
     // ---- one-time set-up: zero U (padding kz >= Kz stays zero) and the transposed source
-    // (rows t >= Nt, channels ci >= Csrc and the over-read pad stay zero); tile tables
-    for (int i = threadIdx.x; i < 2 * Cs * Kt * Kzp; i += NTH) ure[i] = from_f32<T>(0.f);
-    if (PW && Csrc > 0)
-        for (int i = threadIdx.x; i < 16 * a.NTQ * ldT; i += NTH) xt[i] = from_f32<T>(0.f);
-    for (int e = threadIdx.x; e < NT * 16; e += NTH) {
-        // column n = 16 j + cc of a group is (zr, co) = divmod(n, Cs)
-        const int zr = e / Cs, co = e - zr * Cs;
-        tcol[e] = (long long)co * ncell + (long long)zr * Nt;
-        tzr[e] = zr;
-        tb[e] = (bpw && (EPI == ZEPI_BLOCK || EPI == ZEPI_BWD)) ? bpw[co] : 0.f;
-    }
-    for (int j = threadIdx.x; j < NT; j += NTH) {
-        // tile j's z values zlo..zhi cover source K entries [zlo Csp, (zhi + 1) Csp): chunks qlo..qhi
-        const int zlo = (16 * j) / Cs, zhi = (16 * j + 15) / Cs;
-        const int qlo = (zlo * Csp) / 16, qhi = ((zhi + 1) * Csp + 15) / 16 - 1;
-        tq[j] = qlo | (PW && Csrc > 0 ? (qhi - qlo + 1) << 16 : 0);
-    }
-    // block-diagonal pointwise weights: wdl[(j SPAN + s) 64 + lane][jj] = Wd[k = 16 (qlo_j + s) + 4 g + jj][16 j + c]
-    if (PW && Csrc > 0)
-        for (int e = threadIdx.x; e < NT * a.SPAN * 64; e += NTH) {
-            const int el = e & 63, js = e >> 6, j = js / a.SPAN, s = js - j * a.SPAN;
-            const int eg = el >> 4, ec = el & 15;
-            const int n = 16 * j + ec, zr = n / Cs, co = n - zr * Cs;
-            const int zlo = (16 * j) / Cs, zhi = (16 * j + 15) / Cs;
-            const int q = (zlo * Csp) / 16 + s, qh = ((zhi + 1) * Csp + 15) / 16 - 1;
-            float v[4];
-#pragma unroll
-            for (int jj = 0; jj < 4; jj++) {
-                const int k = 16 * q + 4 * eg + jj, zs = k / Csp, ci = k - zs * Csp;
-                float x = 0.f;
-                if (q <= qh && zs == zr && ci < Csrc)
-                    // BLOCK/BWD: co = o, ci = i: W_pw[o][i];  ADJ: co = i, ci = o: W_pw[o][i]
-                    x = EPI == ZEPI_ADJ ? wpw[ci * Cs + co] : wpw[co * Csrc + ci];
-                v[jj] = x;
-            }
-            wdl[e] = op_from4<T>(v[0], v[1], v[2], v[3]);
-        }
+    // (rows t >= Nt, channels ci >= Csrc and the over-read pad stay zero)
+    for (int i = threadIdx.x; i < a.uim_off + Cs * Kt * Kzp; i += NTH) ure[i] = from_f32<T>(0.f);
+    if (has_src)
+        for (int i = threadIdx.x; i < 16 * NTQ * ldT; i += NTH) xt[i] = from_f32<T>(0.f);
 
-    // constant fragments: t basis (A of the synthesis part)
-    Op ta[2][NTT], tal[2][NTT];
+    // ---- this wave's tile: j = w mod NT, groups r, r + R, ...
+    const int tj = w % NT, tr = w / NT;
+    // lane column n = 16 tj + c is (zr, co) = divmod(n, Cs)
+    const int zr = (16 * tj + c) / Cs, co = 16 * tj + c - zr * Cs;
+    // the tile's z values zlo..zhi cover source K entries [zlo Csp, (zhi + 1) Csp): chunks qlo .. qlo + nq - 1
+    const int zlo = (16 * tj) / Cs, zhi = (16 * tj + 15) / Cs;
+    const int qlo = (zlo * Csp) / 16;
+    const int nq = has_src ? ((zhi + 1) * Csp + 15) / 16 - qlo : 0;
+    // block-diagonal pointwise weights wd[s][jj] = Wd[k = 16 (qlo + s) + 4 g + jj][n]
+    Op wd[SPAN];
 #pragma unroll
-    for (int mt = 0; mt < 2; mt++)
+    for (int s = 0; s < SPAN; s++) {
+        float v[4];
+#pragma unroll
+        for (int jj = 0; jj < 4; jj++) {
+            const int k = 16 * (qlo + s) + 4 * g + jj, zs = k / (Csp > 0 ? Csp : 1), ci = k - zs * Csp;
+            float x = 0.f;
+            if (s < nq && zs == zr && ci < Csrc)
+                // BLOCK/BWD: co = o, ci = i: W_pw[o][i];  ADJ: co = i, ci = o: W_pw[o][i]
+                x = EPI == ZEPI_ADJ ? wpw[ci * Cs + co] : wpw[co * Csrc + ci];
+            v[jj] = x;
+        }
+        wd[s] = op_from4<T>(v[0], v[1], v[2], v[3]);
+    }
+    const float bj = (bpw && (EPI == ZEPI_BLOCK || EPI == ZEPI_BWD)) ? bpw[co] : 0.f;
+    // t basis (A of the synthesis part)
+    Op ta[NTQ][NTT], tal[NTQ][NTT];
+#pragma unroll
+    for (int mt = 0; mt < NTQ; mt++)
 #pragma unroll
         for (int q = 0; q < NTT; q++) {
-            ta[mt][q] = mt < a.NTQ ? tabT[(mt * NTT + q) * 64 + lane] : op_zero<T>();
-            if (SPLIT) tal[mt][q] = mt < a.NTQ ? tabT_lo[(mt * NTT + q) * 64 + lane] : op_zero<T>();
+            ta[mt][q] = tabT[(mt * NTT + q) * 64 + lane];
+            if (SPLIT) tal[mt][q] = tabT_lo[(mt * NTT + q) * 64 + lane];
         }
-    // EPI_BWD: gW^T tiles [mi][nc] (rows i, columns o) and per-lane bias-gradient partials
-    f4v gwacc[EPI == ZEPI_BWD ? MAXC : 1][EPI == ZEPI_BWD ? MAXC : 1];
-    float gbacc[EPI == ZEPI_BWD ? MAXC : 1];
-    if (EPI == ZEPI_BWD) {
+    // EPI_BWD: C tiles [s] (rows (z', i) = 16 (qlo + s) + 4 g + r, column n) and the bias gradient of column n
+    constexpr int NGW = EPI == ZEPI_BWD ? SPAN : 1;
+    f4v gwacc[NGW];
+    float gbacc = 0.f;
 #pragma unroll
-        for (int mi = 0; mi < MAXC; mi++)
-#pragma unroll
-            for (int nc = 0; nc < MAXC; nc++) gwacc[mi][nc] = f4_zero();
-#pragma unroll
-        for (int nc = 0; nc < MAXC; nc++) gbacc[nc] = 0.f;
-    }
+    for (int s = 0; s < NGW; s++) gwacc[s] = f4_zero();
 
     // U staging: thread -> fixed (kz, kt) entry r, channels strided by u_cstep
     const bool u_one = KK <= NTH;
@@ -151,13 +157,13 @@ __global__ void __launch_bounds__(64 * NW) k_zt_epi(const float2 *__restrict__ u
     const int u_r0 = u_one ? (int)threadIdx.x % KK : (int)threadIdx.x;
     const int u_c0 = u_one ? (int)threadIdx.x / KK : 0;
     const bool u_ok = u_one ? (int)threadIdx.x < u_cstep * KK : true;
-    // source staging: thread -> fixed (zl, t4) pair (4 consecutive t), channels strided
+    // source staging: thread -> (zl, t4) pairs (4 consecutive t), channels strided by sp_cstep
     const int nt4 = Nt / 4, npair = ZC * nt4;
-    const int sp_cstep = NTH / npair;  // threads per pair (>= 2 since Nt <= 32)
-    const bool sp_ok = (int)threadIdx.x < sp_cstep * npair;
-    const int sp_pair = threadIdx.x % npair, sp_c0 = threadIdx.x / npair;
-    const int sp_zl = sp_pair / nt4, sp_t4 = sp_pair % nt4;
-    const int ngroups = ZC / ZG, npairs = ngroups * NT;
+    const bool sp_one = npair <= NTH;
+    const int sp_cstep = sp_one ? NTH / npair : 1;
+    const bool sp_ok = sp_one ? (int)threadIdx.x < sp_cstep * npair : true;
+    const int sp_c0 = sp_one ? (int)threadIdx.x / npair : 0;
+    const int ngroups = ZC / ZG;
     const int QH = a.QZ / 2;
     __syncthreads();
 
@@ -166,14 +172,16 @@ __global__ void __launch_bounds__(64 * NW) k_zt_epi(const float2 *__restrict__ u
         const int b = (int)(pl / nxy);
         const long long xy = pl % nxy;
         const T *srcp = src + (long long)b * Csrc * ncell + xy * plane;
-        const long long obase = (long long)b * Cs * ncell + xy * plane;
+        // element offset of this lane's column (zr, co) at z = 0 and t = 4 g
+        const long long ecol = ((long long)b * Cs + co) * ncell + xy * plane + (long long)zr * Nt + 4 * g;
         __syncthreads();  // previous plane's readers of U are done
-        // ---- phase 0: U of every channel, transposed to [c][kt][kz]
+        // ---- phase 0: U of every channel, to [c][kz / 4][kt][kz % 4]
         if (u_ok)
             for (int r = u_r0; r < KK; r += (u_one ? KK : NTH)) {
                 const int kz = r / Kt, kt = r - kz * Kt;
                 const float2 *up = u + ((long long)b * Cs * nxy + xy) * KK + r;
-                T *ur = ure + (size_t)kt * Kzp + kz, *ui = uim + (size_t)kt * Kzp + kz;
+                const size_t ul = ((size_t)(kz >> 2) * Kt + kt) * 4 + (kz & 3);
+                T *ur = ure + ul, *ui = uim + ul;
                 for (int cs = u_c0; cs < Cs; cs += u_cstep) {
                     const float2 v = up[(long long)cs * nxy * KK];
                     ur[(size_t)cs * Kt * Kzp] = from_f32<T>(v.x);
@@ -182,25 +190,42 @@ __global__ void __launch_bounds__(64 * NW) k_zt_epi(const float2 *__restrict__ u
             }
         for (int zc0 = 0; zc0 < Nz; zc0 += ZC) {
             __syncthreads();  // U staged / previous chunk's V and source consumed
+            // early loads of the first tile's epilogue operand (gy, or the accumulated output)
+            Op ext[NTQ];
+            auto load_ext = [&](int z0, Op(&e)[NTQ]) {
+#pragma unroll
+                for (int mt = 0; mt < NTQ; mt++) {
+                    e[mt] = op_zero<T>();
+                    const bool ok = z0 < Nz && z0 + zr < Nz && 16 * mt + 4 * g < Nt;
+                    const long long ei = ecol + (long long)z0 * Nt + 16 * mt;
+                    if (EPI == ZEPI_BWD && ok) e[mt] = *reinterpret_cast<const Op *>(gy + ei);
+                    if (EPI == ZEPI_ADJ && ok && a.accumulate) e[mt] = *reinterpret_cast<const Op *>(out + ei);
+                }
+            };
+            if (EPI == ZEPI_BWD || EPI == ZEPI_ADJ) load_ext(zc0 + tr * ZG, ext);
             // source chunk -> LDS transposed [t][(zl, ci)]: thread owns pair (zl, t4), strides over channels
-            if (PW && Csrc > 0 && sp_ok) {
-                const bool zin = zc0 + sp_zl < Nz;
-                const T *sp = srcp + (long long)(zc0 + sp_zl) * Nt + 4 * sp_t4;
-                T *dl = xt + (size_t)(4 * sp_t4) * ldT + sp_zl * Csp;
-                for (int ci0 = sp_c0; ci0 < Csrc; ci0 += 4 * sp_cstep) {
-                    Op vv[4];
+            if (has_src && sp_ok) {
+                for (int pr = sp_one ? (int)threadIdx.x % npair : (int)threadIdx.x; pr < npair;
+                     pr += (sp_one ? npair : NTH)) {
+                    const int zl = pr / nt4, t4 = pr - zl * nt4;
+                    const bool zin = zc0 + zl < Nz;
+                    const T *sp = srcp + (long long)(zc0 + zl) * Nt + 4 * t4;
+                    T *dl = xt + (size_t)(4 * t4) * ldT + zl * Csp;
+                    for (int ci0 = sp_c0; ci0 < Csrc; ci0 += 4 * sp_cstep) {
+                        Op vv[4];
 #pragma unroll
-                    for (int k = 0; k < 4; k++) {
-                        const int ci = ci0 + k * sp_cstep;
-                        vv[k] = (zin && ci < Csrc) ? *reinterpret_cast<const Op *>(sp + (long long)ci * ncell)
-                                                   : op_zero<T>();
-                    }
+                        for (int k = 0; k < 4; k++) {
+                            const int ci = ci0 + k * sp_cstep;
+                            vv[k] = (zin && ci < Csrc) ? *reinterpret_cast<const Op *>(sp + (long long)ci * ncell)
+                                                       : op_zero<T>();
+                        }
 #pragma unroll
-                    for (int k = 0; k < 4; k++) {
-                        const int ci = ci0 + k * sp_cstep;
-                        if (ci < Csrc) {
+                        for (int k = 0; k < 4; k++) {
+                            const int ci = ci0 + k * sp_cstep;
+                            if (ci < Csrc) {
 #pragma unroll
-                            for (int jj = 0; jj < 4; jj++) op_put(dl + (size_t)jj * ldT + ci, vv[k], jj);
+                                for (int jj = 0; jj < 4; jj++) op_put(dl + (size_t)jj * ldT + ci, vv[k], jj);
+                            }
                         }
                     }
                 }
@@ -212,19 +237,21 @@ __global__ void __launch_bounds__(64 * NW) k_zt_epi(const float2 *__restrict__ u
                 const int ri = NTT == 1 ? (c >> 3) : mt;
                 const int kt = NTT == 1 ? (c & 7) : c;
                 const bool krow = kt < Kt;
-                const size_t roff = ((size_t)cs * Kt + (krow ? kt : 0)) * Kzp + 4 * g;
+                // row (ri, kt), K entries kz = 16 q + 4 g + jj: one 4-vector at [cs][4 q + g][kt][.]
+                const size_t roff = ((size_t)cs * Kt * Kzp) + ((size_t)g * Kt + (krow ? kt : 0)) * 4;
                 const T *p_cos = (ri == 0 ? ure : uim) + roff;  // multiplies cos
                 const T *p_sin = (ri == 0 ? uim : ure) + roff;  // multiplies sin (negated for ri = 0)
+                const int qstep = 16 * Kt;
                 f4v acc = f4_zero();
                 for (int q = 0; q < QH; q++) {
-                    const Op av = krow ? *reinterpret_cast<const Op *>(p_cos + 16 * q) : op_zero<T>();
+                    const Op av = krow ? *reinterpret_cast<const Op *>(p_cos + qstep * q) : op_zero<T>();
                     const int ti = (zg * a.QZ + q) * 64 + lane;
                     acc = mma16(av, tabZ[ti], acc);
                     if (SPLIT) acc = mma16(av, tabZ_lo[ti], acc);
                 }
                 for (int q = 0; q < QH; q++) {
                     const Op av =
-                        krow ? op_sign(*reinterpret_cast<const Op *>(p_sin + 16 * q), ri == 0) : op_zero<T>();
+                        krow ? op_sign(*reinterpret_cast<const Op *>(p_sin + qstep * q), ri == 0) : op_zero<T>();
                     const int ti = (zg * a.QZ + QH + q) * 64 + lane;
                     acc = mma16(av, tabZ[ti], acc);
                     if (SPLIT) acc = mma16(av, tabZ_lo[ti], acc);
@@ -234,55 +261,48 @@ __global__ void __launch_bounds__(64 * NW) k_zt_epi(const float2 *__restrict__ u
                 store4(vl + ((size_t)c * Cs + cs) * ldv + 16 * mt + 4 * g, v);
             }
             __syncthreads();
-            // ---- phase 2: (group gi, tile j) pairs p = gi NT + j, spread over the waves
-            int gi = w / NT, j = w - (w / NT) * NT;
-            for (int p = w; p < npairs; p += NW) {
+            // ---- phase 2: this wave's tile of groups tr, tr + R, ...
+            for (int gi = tr; gi < ngroups; gi += R) {
                 const int z0 = zc0 + gi * ZG;
-                if (z0 < Nz) {
-                    const int tqv = tq[j], qlo = tqv & 0xffff, nq = tqv >> 16;
-                    const long long e0 = obase + tcol[16 * j + c] + (long long)z0 * Nt + 4 * g;
-                    const bool zok = z0 + tzr[16 * j + c] < Nz;
-                    const float bj = tb[16 * j + c];
-                    // early loads of the epilogue's second operand (gy, or the accumulated output)
-                    Op ext[2];
+                if (z0 >= Nz) break;
+                Op ext_next[NTQ];
+                if (EPI == ZEPI_BWD || EPI == ZEPI_ADJ) load_ext(gi + R < ngroups ? z0 + R * ZG : Nz, ext_next);
+                // operands: V columns (B of the synthesis) and the transposed source (A of the 1x1)
+                const int vrow = gi * ZG * Cs + 16 * tj + c;
+                Op bv[NTT];
 #pragma unroll
-                    for (int mt = 0; mt < 2; mt++) {
-                        ext[mt] = op_zero<T>();
-                        const bool ok = zok && mt < a.NTQ && 16 * mt + 4 * g < Nt;
-                        if (EPI == ZEPI_BWD && ok) ext[mt] = *reinterpret_cast<const Op *>(gy + e0 + 16 * mt);
-                        if (EPI == ZEPI_ADJ && ok && a.accumulate)
-                            ext[mt] = *reinterpret_cast<const Op *>(out + e0 + 16 * mt);
-                    }
-                    f4v acc[2] = {f4_zero(), f4_zero()};
-                    const int vrow = gi * ZG * Cs + 16 * j + c;
+                for (int q = 0; q < NTT; q++) bv[q] = *reinterpret_cast<const Op *>(vl + (size_t)vrow * ldv + 16 * q + 4 * g);
+                // A[t = 16 mt + c][k = 16 (qlo + s) + 4 g + jj]
+                const T *xa = xt + (size_t)c * ldT + gi * ZG * Csp + 16 * qlo + 4 * g;
+                Op av[has_src_c<EPI>() ? SPAN : 1][NTQ];
+                if (PW) {
+#pragma unroll
+                    for (int s = 0; s < SPAN; s++)
+#pragma unroll
+                        for (int mt = 0; mt < NTQ; mt++)
+                            av[s][mt] = has_src ? *reinterpret_cast<const Op *>(xa + (size_t)16 * mt * ldT + 16 * s)
+                                                : op_zero<T>();
+                }
+                f4v acc[NTQ];
+#pragma unroll
+                for (int mt = 0; mt < NTQ; mt++) {
+                    acc[mt] = f4_zero();
 #pragma unroll
                     for (int q = 0; q < NTT; q++) {
-                        const Op bv = *reinterpret_cast<const Op *>(vl + (size_t)vrow * ldv + 16 * q + 4 * g);
-#pragma unroll
-                        for (int mt = 0; mt < 2; mt++)
-                            if (mt < a.NTQ) {
-                                acc[mt] = mma16(ta[mt][q], bv, acc[mt]);
-                                if (SPLIT) acc[mt] = mma16(tal[mt][q], bv, acc[mt]);
-                            }
+                        acc[mt] = mma16(ta[mt][q], bv[q], acc[mt]);
+                        if (SPLIT) acc[mt] = mma16(tal[mt][q], bv[q], acc[mt]);
                     }
-                    if (PW && nq > 0) {
-                        const T *xa = xt + (size_t)c * ldT + gi * ZG * Csp + 16 * qlo + 4 * g;
-                        const Op *wa = wdl + (size_t)j * a.SPAN * 64 + lane;
-                        for (int s = 0; s < nq; s++) {
-                            const Op wv = wa[s * 64];
+                    if (PW) {
 #pragma unroll
-                            for (int mt = 0; mt < 2; mt++)
-                                if (mt < a.NTQ) {
-                                    // A[t = 16 mt + c][k = 16 (qlo + s) + 4 g + jj]
-                                    const Op av = *reinterpret_cast<const Op *>(xa + (size_t)16 * mt * ldT + 16 * s);
-                                    acc[mt] = mma16(av, wv, acc[mt]);
-                                }
-                        }
+                        for (int s = 0; s < SPAN; s++) acc[mt] = mma16(av[s][mt], wd[s], acc[mt]);
                     }
-                    // epilogue: acc[mt][r] is (t = 16 mt + 4 g + r, column 16 j + c)
+                }
+                // epilogue: acc[mt][r] is (t = 16 mt + 4 g + r, column n)
+                const bool zok = z0 + zr < Nz;
 #pragma unroll
-                    for (int mt = 0; mt < 2; mt++) {
-                        const bool ok = zok && mt < a.NTQ && 16 * mt + 4 * g < Nt;
+                for (int mt = 0; mt < NTQ; mt++) {
+                    {
+                        const bool ok = zok && 16 * mt + 4 * g < Nt;
                         float v[4];
 #pragma unroll
                         for (int r = 0; r < 4; r++) v[r] = acc[mt][r];
@@ -291,73 +311,73 @@ __global__ void __launch_bounds__(64 * NW) k_zt_epi(const float2 *__restrict__ u
                             for (int r = 0; r < 4; r++) v[r] = gelu_fast(v[r] + bj);
                         } else if (EPI == ZEPI_BWD) {
 #pragma unroll
-                            for (int r = 0; r < 4; r++) v[r] = op_get(ext[mt], r) * gelu_grad_fast(v[r] + bj);
+                            for (int r = 0; r < 4; r++) {
+                                v[r] = ok ? op_get(ext[mt], r) * gelu_grad_fast(v[r] + bj) : 0.f;
+                                gbacc += v[r];
+                            }
+                            acc[mt] = f4v{v[0], v[1], v[2], v[3]};  // gradient tile, B of the product below
                         } else if (EPI == ZEPI_ADJ) {
 #pragma unroll
                             for (int r = 0; r < 4; r++) v[r] += op_get(ext[mt], r);
                         }
-                        if (ok) store4(out + e0 + 16 * mt, v);
+                        if (ok) store4(out + ecol + (long long)z0 * Nt + 16 * mt, v);
                     }
                 }
-                j += NW;
-                while (j >= NT) {
-                    j -= NT;
-                    gi++;
-                }
-            }
-            if (EPI == ZEPI_BWD) {
-                // weight-gradient product of this chunk, one z per wave at a time:
-                // gW^T[i][o] += sum_t x[i][z][t] gz[o][z][t]  (A rows i, B columns o, K = t)
-                __syncthreads();  // the chunk's gz is written
-                const int Ci = Csrc, Co = Cs;
-                for (int zl = w; zl < ZC && zc0 + zl < Nz; zl += NW) {
-                    const long long zo = xy * plane + (long long)(zc0 + zl) * Nt + 4 * g;
+                if (EPI == ZEPI_BWD) {
+                    // C[(z', i) = 16 (qlo + s) + 4 g + r][n] += sum_t x[z'][i][t] gz[n][t]; K chunk = t tile mt
+                    const T *xg = xt + (size_t)(4 * g) * ldT + gi * ZG * Csp + 16 * qlo + c;
 #pragma unroll
-                    for (int mt = 0; mt < 2; mt++) {
-                        if (mt < a.NTQ && 16 * mt + 4 * g < Nt) {
-                            Op ax[MAXC], bz[MAXC];
+                    for (int mt = 0; mt < NTQ; mt++) {
+                        const Op bg = to_op<T>(acc[mt]);
 #pragma unroll
-                            for (int m = 0; m < MAXC; m++) {
-                                const int ch = 16 * m + c;
-                                ax[m] = ch < Ci ? *reinterpret_cast<const Op *>(src + ((long long)b * Ci + ch) * ncell +
-                                                                                 zo + 16 * mt)
-                                                : op_zero<T>();
-                                bz[m] = ch < Co ? *reinterpret_cast<const Op *>(out + ((long long)b * Co + ch) * ncell +
-                                                                                 zo + 16 * mt)
-                                                : op_zero<T>();
-                            }
-#pragma unroll
-                            for (int nc = 0; nc < MAXC; nc++) {
-                                gbacc[nc] += (op_get(bz[nc], 0) + op_get(bz[nc], 1)) + (op_get(bz[nc], 2) + op_get(bz[nc], 3));
-#pragma unroll
-                                for (int mi = 0; mi < MAXC; mi++) gwacc[mi][nc] = mma16(ax[mi], bz[nc], gwacc[mi][nc]);
-                            }
+                        for (int s = 0; s < NGW; s++) {
+                            const Op ax = op_gather(xg + (size_t)16 * mt * ldT + 16 * s, ldT);
+                            gwacc[s] = mma16(ax, bg, gwacc[s]);
                         }
                     }
+                }
+                if (EPI == ZEPI_BWD || EPI == ZEPI_ADJ) {
+#pragma unroll
+                    for (int mt = 0; mt < NTQ; mt++) ext[mt] = ext_next[mt];
                 }
             }
         }
     }
     if (EPI == ZEPI_BWD) {
-        // partial sums of this wave: part[(block NW + w)][o][0..Ci-1] = gw, [o][Ci] = gb
+        // gw[o][i] = sum over waves and z of the z' = z entries of the C tiles, gb[o] likewise.
+        // The slots go to LDS as [wave][s][r][lane] (gb: [wave][lane] after the sum over g), then
+        // one thread per (o, i) adds its slots in a fixed order: waves, then z.
         const int Ci = Csrc, Co = Cs;
-        float *pw = part + ((size_t)blockIdx.x * NW + w) * Co * (Ci + 1);
+        float *slots = reinterpret_cast<float *>(smem);
+        float *gbs = slots + (size_t)NW * SPAN * 4 * 64;
+        gbacc += __shfl_xor(gbacc, 16);
+        gbacc += __shfl_xor(gbacc, 32);
+        __syncthreads();
 #pragma unroll
-        for (int mi = 0; mi < MAXC; mi++)
+        for (int s = 0; s < SPAN; s++)
 #pragma unroll
-            for (int nc = 0; nc < MAXC; nc++)
-#pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const int i = 16 * mi + 4 * g + r, o = 16 * nc + c;
-                    if (i < Ci && o < Co) pw[o * (Ci + 1) + i] = gwacc[mi][nc][r];
+            for (int r = 0; r < 4; r++) slots[((size_t)(w * SPAN + s) * 4 + r) * 64 + lane] = gwacc[s][r];
+        gbs[w * 64 + lane] = gbacc;
+        __syncthreads();
+        float *pw = part + (size_t)blockIdx.x * Co * (Ci + 1);
+        for (int e = threadIdx.x; e < Co * (Ci + 1); e += NTH) {
+            const int o = e / (Ci + 1), i = e - o * (Ci + 1);
+            float sum = 0.f;
+            for (int ww = 0; ww < NW; ww++) {
+                const int j = ww % NT;
+                const int q0 = ((16 * j) / Cs * Csp) / 16;
+                for (int zz = 0; zz < ZG; zz++) {
+                    const int cc = zz * Cs + o - 16 * j;  // lane column of (zz, o) in tile j
+                    if (cc < 0 || cc >= 16) continue;
+                    if (i == Ci) {
+                        sum += gbs[ww * 64 + cc];
+                    } else {
+                        const int k = zz * Csp + i, sq = k / 16 - q0, gg = (k % 16) / 4, rr = k % 4;
+                        sum += slots[((size_t)(ww * SPAN + sq) * 4 + rr) * 64 + 16 * gg + cc];
+                    }
                 }
-#pragma unroll
-        for (int nc = 0; nc < MAXC; nc++) {
-            float s = gbacc[nc];
-            s += __shfl_xor(s, 16);
-            s += __shfl_xor(s, 32);
-            const int o = 16 * nc + c;
-            if (g == 0 && o < Co) pw[o * (Ci + 1) + Ci] = s;
+            }
+            pw[e] = sum;
         }
     }
 }
@@ -379,7 +399,7 @@ static int gcd_int(int a, int b)
 
 static size_t al16(size_t v) { return (v + 15) / 16 * 16; }
 
-// Geometry and LDS carve-up of one launch; returns the LDS bytes.
+// Geometry and LDS carve-up of one launch; returns the LDS bytes (0: shape not supported).
 static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, ZtArgs &a)
 {
     a = ZtArgs{};
@@ -398,36 +418,39 @@ static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, ZtArgs &a)
     a.NTQ = (d.N[3] + 15) / 16;
     a.ZG = 16 / gcd_int(Cs, 16);
     a.NT = a.ZG * Cs / 16;
-    a.SPAN = 1;
-    for (int j = 0; j < a.NT; j++) {
+    if (a.NT > kZtMaxWaves) return 0;
+    // waves per tile index: about 8 waves in all (at most 16), never more than there are groups
+    a.R = std::max(1, std::min(16 / a.ZG, (8 + a.NT - 1) / a.NT));
+    while (a.NT * a.R > kZtMaxWaves) a.R--;
+    int span = 1;
+    for (int j = 0; j < a.NT && Csrc > 0; j++) {
         const int zlo = (16 * j) / Cs, zhi = (16 * j + 15) / Cs;
         const int qlo = (zlo * a.Csp) / 16, qhi = ((zhi + 1) * a.Csp + 15) / 16 - 1;
-        a.SPAN = std::max(a.SPAN, qhi - qlo + 1);
+        span = std::max(span, qhi - qlo + 1);
     }
-    a.ldT = 16 * a.Csp + 12;  // + over-read of the last group's last K chunk
+    if (span > kZtMaxSpan) return 0;
+    a.SPAN = Csrc == 0 ? 1 : (span <= 2 ? 2 : 4);
+    // row stride of the transposed source: every tile reads SPAN chunks from its first one, at
+    // most 15 Csp + 16 SPAN columns in; rows end with the over-read of the last group
+    a.ldT = (std::max(16 * a.Csp + 12, 15 * a.Csp + 16 * a.SPAN) + 3) / 4 * 4;
     const int ntt = d.K[3] <= 8 ? 1 : 2;
-    size_t off = al16((size_t)2 * Cs * a.Kt * a.Kzp * elem);
+    // imaginary plane at a word offset = 16 (mod 32) from the real one
+    a.uim_off = Cs * a.Kt * a.Kzp;
+    while (((size_t)a.uim_off * elem / 4) % 32 != 16) a.uim_off += 16 / elem;
+    size_t off = al16(((size_t)a.uim_off + (size_t)Cs * a.Kt * a.Kzp) * elem);
     a.off_v = (int)off;
     off += al16((size_t)16 * Cs * (16 * ntt + 4) * elem);
     a.off_x = (int)off;
     if (Csrc) off += al16((size_t)16 * a.NTQ * a.ldT * elem);
-    a.off_wd = (int)off;
-    if (Csrc) off += (size_t)a.NT * a.SPAN * 64 * 4 * elem;
-    a.off_tcol = (int)off;
-    off += al16((size_t)a.NT * 16 * 8);
-    a.off_tzr = (int)off;
-    off += al16((size_t)a.NT * 16 * 4);
-    a.off_tb = (int)off;
-    off += al16((size_t)a.NT * 16 * 4);
-    a.off_tq = (int)off;
-    off += al16((size_t)a.NT * 4);
-    return off;
+    // the BWD reduction at the end reuses the front: [waves][span][4][64] slots + [waves][64]
+    return std::max(off, (size_t)a.NT * a.R * (a.SPAN * 4 + 1) * 64 * sizeof(float));
 }
 
 static bool zt_pair_ok(const Dims &d, int Cs, int Csrc, int elem)
 {
     ZtArgs a;
-    return zt_layout(d, Cs, Csrc, elem, a) <= 160 * 1024;
+    const size_t lds = zt_layout(d, Cs, Csrc, elem, a);
+    return lds > 0 && lds <= 160 * 1024;
 }
 
 bool zt_supported(const Dims &d, int dtype)
@@ -440,56 +463,38 @@ bool zt_supported(const Dims &d, int dtype)
            zt_pair_ok(d, d.Ci, 0, elem);
 }
 
-constexpr int kZtWaves = 8;
-
 int zt_grid(const Dims &d) { return (int)std::min<long long>((long long)d.B * d.N[0] * d.N[1], 2048); }
-int zt_partial_rows(const Dims &d) { return zt_grid(d) * kZtWaves; }
+int zt_partial_rows(const Dims &d) { return zt_grid(d); }
 
-template <typename T, int EPI, int NTT, int MAXC>
+template <typename T, int EPI, int NTT, int NTQ, int SPAN, int MAXW>
 static hipError_t launch_zt_t(const Dims &d, int Cs, int Csrc, int accumulate, const float2 *u, T *out,
                               const T *src, const T *gy, const float *wpw, const float *bpw, float *part,
                               const ZtTabs &tb, hipStream_t st, int *rows_used)
 {
     typedef typename OpOf<T>::type Op;
     constexpr bool split = sizeof(T) == 2;
-    constexpr int NW = kZtWaves;
     ZtArgs a;
     const size_t lds = zt_layout(d, Cs, Csrc, sizeof(T), a);
+    if (lds == 0) return hipErrorInvalidValue;
     a.accumulate = accumulate;
-    auto kern = k_zt_epi<T, EPI, NTT, split, NW, MAXC>;
+    const int nth = 64 * a.NT * a.R;
+    if (a.NT * a.R > MAXW || a.NTQ != NTQ || (EPI != ZEPI_PLAIN && a.SPAN > SPAN)) return hipErrorInvalidValue;
+    auto kern = k_zt_epi<T, EPI, NTT, NTQ, SPAN, split, MAXW>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     // persistent grid: as many workgroups as can be resident at once (at most one per plane)
     int grid = zt_grid(d);
     int per_cu = 0, dev = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), 64 * NW, lds) ==
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), nth, lds) ==
             hipSuccess &&
         hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && per_cu > 0)
         grid = std::min(grid, per_cu * ncu);
-    if (rows_used) *rows_used = grid * NW;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * NW), lds, st, u, out, src, gy, wpw, bpw, part, (const Op *)tb.z,
+    if (rows_used) *rows_used = grid;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(nth), lds, st, u, out, src, gy, wpw, bpw, part, (const Op *)tb.z,
                        (const Op *)tb.z_lo, (const Op *)tb.t, (const Op *)tb.t_lo, a);
     return hipGetLastError();
-}
-
-template <typename T, int EPI>
-static hipError_t launch_zt_e(const Dims &d, int Cs, int Csrc, int accumulate, const float2 *u, T *out, const T *src,
-                              const T *gy, const float *wpw, const float *bpw, float *part, const ZtTabs &tb,
-                              hipStream_t st, int *rows_used)
-{
-    const bool ntt1 = d.K[3] <= 8;
-    const bool c2 = std::max(Cs, Csrc) <= 32;
-    if (EPI != ZEPI_BWD) {
-        return ntt1 ? launch_zt_t<T, EPI, 1, 1>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw, bpw, part, tb, st, rows_used)
-                    : launch_zt_t<T, EPI, 2, 1>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw, bpw, part, tb, st, rows_used);
-    }
-    if (ntt1)
-        return c2 ? launch_zt_t<T, EPI, 1, 2>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw, bpw, part, tb, st, rows_used)
-                  : launch_zt_t<T, EPI, 1, 4>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw, bpw, part, tb, st, rows_used);
-    return c2 ? launch_zt_t<T, EPI, 2, 2>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw, bpw, part, tb, st, rows_used)
-              : launch_zt_t<T, EPI, 2, 4>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw, bpw, part, tb, st, rows_used);
 }
 
 // epi: ZEPI_*; Cs = output/spectral channels, Csrc = pointwise source channels.
@@ -499,12 +504,34 @@ hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const float2 *u, 
                      const float *wpw, const float *bpw, float *part, const ZtTabs &tb, int accumulate, hipStream_t st,
                      int *rows_used)
 {
-    switch (epi) {
-    case ZEPI_PLAIN: return launch_zt_e<T, ZEPI_PLAIN>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw, bpw, part, tb, st, rows_used);
-    case ZEPI_BLOCK: return launch_zt_e<T, ZEPI_BLOCK>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw, bpw, part, tb, st, rows_used);
-    case ZEPI_BWD: return launch_zt_e<T, ZEPI_BWD>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw, bpw, part, tb, st, rows_used);
-    default: return launch_zt_e<T, ZEPI_ADJ>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw, bpw, part, tb, st, rows_used);
+    ZtArgs a;
+    if (zt_layout(d, Cs, Csrc, sizeof(T), a) == 0) return hipErrorInvalidValue;
+    const bool w10 = a.NT * a.R <= 10;
+    const int sel = (d.K[3] <= 8 ? 0 : 4) + (a.NTQ == 1 ? 0 : 2) + (a.SPAN <= 2 ? 0 : 1);
+#define FNO_ZT_W(E, NTT_, NTQ_, SPAN_)                                                                              \
+    return w10 ? launch_zt_t<T, E, NTT_, NTQ_, SPAN_, 10>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw, bpw, part, \
+                                                          tb, st, rows_used)                                        \
+               : launch_zt_t<T, E, NTT_, NTQ_, SPAN_, kZtMaxWaves>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw,   \
+                                                                   bpw, part, tb, st, rows_used)
+#define FNO_ZT(E)                                                                                                   \
+    switch (E == ZEPI_PLAIN ? sel & 6 : sel) {                                                                      \
+    case 0: FNO_ZT_W(E, 1, 1, 2);                                                                                   \
+    case 1: FNO_ZT_W(E, 1, 1, 4);                                                                                   \
+    case 2: FNO_ZT_W(E, 1, 2, 2);                                                                                   \
+    case 3: FNO_ZT_W(E, 1, 2, 4);                                                                                   \
+    case 4: FNO_ZT_W(E, 2, 1, 2);                                                                                   \
+    case 5: FNO_ZT_W(E, 2, 1, 4);                                                                                   \
+    case 6: FNO_ZT_W(E, 2, 2, 2);                                                                                   \
+    default: FNO_ZT_W(E, 2, 2, 4);                                                                                  \
     }
+    switch (epi) {
+    case ZEPI_PLAIN: FNO_ZT(ZEPI_PLAIN);
+    case ZEPI_BLOCK: FNO_ZT(ZEPI_BLOCK);
+    case ZEPI_BWD: FNO_ZT(ZEPI_BWD);
+    default: FNO_ZT(ZEPI_ADJ);
+    }
+#undef FNO_ZT_W
+#undef FNO_ZT
 }
 
 template hipError_t launch_zt<float>(int, const Dims &, int, int, const float2 *, float *, const float *,
