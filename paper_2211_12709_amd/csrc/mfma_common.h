@@ -113,4 +113,40 @@ __device__ __forceinline__ void store4(__bf16 *p, const float (&v)[4])
     *reinterpret_cast<s4v *>(p) = s4v{bf16_bits(v[0]), bf16_bits(v[1]), bf16_bits(v[2]), bf16_bits(v[3])};
 }
 
+// 4x4 transpose: r[j] = {v[0][j], v[1][j], v[2][j], v[3][j]} (element j of four fragments).
+__device__ __forceinline__ void op_transpose4(const f4v (&v)[4], f4v (&r)[4])
+{
+#pragma unroll
+    for (int j = 0; j < 4; j++) r[j] = f4v{v[0][j], v[1][j], v[2][j], v[3][j]};
+}
+__device__ __forceinline__ void op_transpose4(const s4v (&v)[4], s4v (&r)[4])
+{
+#pragma unroll
+    for (int j = 0; j < 4; j++) r[j] = s4v{v[0][j], v[1][j], v[2][j], v[3][j]};
+}
+
+// 8 consecutive activations <-> two fragments (one 16-byte access for bfloat16, two for float).
+typedef short s8v __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ void load8(const float *p, f4v &a, f4v &b)
+{
+    a = *reinterpret_cast<const f4v *>(p);
+    b = *reinterpret_cast<const f4v *>(p + 4);
+}
+__device__ __forceinline__ void load8(const __bf16 *p, s4v &a, s4v &b)
+{
+    const s8v t = *reinterpret_cast<const s8v *>(p);
+    a = s4v{t[0], t[1], t[2], t[3]};
+    b = s4v{t[4], t[5], t[6], t[7]};
+}
+__device__ __forceinline__ void store8(float *p, const float (&v)[2][4])
+{
+    *reinterpret_cast<f4v *>(p) = f4v{v[0][0], v[0][1], v[0][2], v[0][3]};
+    *reinterpret_cast<f4v *>(p + 4) = f4v{v[1][0], v[1][1], v[1][2], v[1][3]};
+}
+__device__ __forceinline__ void store8(__bf16 *p, const float (&v)[2][4])
+{
+    *reinterpret_cast<s8v *>(p) = s8v{bf16_bits(v[0][0]), bf16_bits(v[0][1]), bf16_bits(v[0][2]), bf16_bits(v[0][3]),
+                                      bf16_bits(v[1][0]), bf16_bits(v[1][1]), bf16_bits(v[1][2]), bf16_bits(v[1][3])};
+}
+
 }  // namespace fno

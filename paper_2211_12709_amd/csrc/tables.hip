@@ -93,9 +93,12 @@ __global__ void k_gen_tab(int kind, TabGeom G, long long n, float *__restrict__ 
             v = ri == 0 ? cos(th) : sin(th);
         }
     } else if (kind == TAB_TI_INV || kind == TAB_TI_ADJ) {
-        // A[t][(ri, kt)] for t tile mt and K chunk q: w cos (ri = 0) / -w sin (ri = 1) of 2 pi kt t / Nt
+        // A[t][(ri, kt)] for t tile mt and K chunk q: w cos (ri = 0) / -w sin (ri = 1) of 2 pi kt t / Nt.
+        // Row c of tile mt is t = 4 NTQ (c / 4) + 4 mt + c % 4 (NTQ = t tiles), so that an output lane
+        // 16 g' + c' holds the 4 NTQ consecutive t = 4 NTQ g' .. of column c' across the tiles.
         const int q = (int)(tile % G.NTT), mt = (int)(tile / G.NTT);
-        const int t = mt * 16 + c, k = 16 * q + 4 * g + j;
+        const int ntq = (G.Nt + 15) / 16;
+        const int t = 4 * ntq * (c >> 2) + 4 * mt + (c & 3), k = 16 * q + 4 * g + j;
         const int ri = G.NTT == 1 ? k / 8 : q;
         const int kt = G.NTT == 1 ? k % 8 : k - 16 * q;
         if (t < G.Nt && kt < G.Kt) {

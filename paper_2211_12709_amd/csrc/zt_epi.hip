@@ -32,6 +32,33 @@ namespace fno {
 
 enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3 };
 
+// Tuning knobs of the launch (defaults are the measured best on MI355X).
+#ifndef FNO_ZT_PREFETCH
+#define FNO_ZT_PREFETCH 0  // load the next z chunk's source during the current chunk's phase 2
+#endif
+#ifndef FNO_ZT_WAVES_BF16
+#define FNO_ZT_WAVES_BF16 5  // waves per SIMD the bfloat16 BLOCK/ADJ/PLAIN kernels are compiled for
+#endif
+#ifndef FNO_ZT_WAVES_BWD
+#define FNO_ZT_WAVES_BWD 4  // the same for the bfloat16 BWD kernel
+#endif
+#ifndef FNO_ZT_WAVES_F32
+#define FNO_ZT_WAVES_F32 3  // the same for every float kernel
+#endif
+// waves per workgroup aimed at (rounded to a multiple of the tile count), per epilogue
+#ifndef FNO_ZT_TARGET_BLOCK
+#define FNO_ZT_TARGET_BLOCK 8
+#endif
+#ifndef FNO_ZT_TARGET_BWD
+#define FNO_ZT_TARGET_BWD 8
+#endif
+#ifndef FNO_ZT_TARGET_ADJ
+#define FNO_ZT_TARGET_ADJ 4  // also PLAIN
+#endif
+#ifndef FNO_ZT_TARGET_F32
+#define FNO_ZT_TARGET_F32 8  // every float epilogue
+#endif
+
 constexpr int kZtMaxWaves = 16;
 constexpr int kZtMaxSpan = 4;
 
@@ -76,16 +103,15 @@ template <int EPI> constexpr bool has_src_c() { return EPI != ZEPI_PLAIN; }
 // NTT: (re/im, kt) tiles (1: Kt <= 8, 2: Kt <= 16).  NTQ: t tiles (1: Nt <= 16, 2: Nt <= 32).
 // SPAN: source K chunks every tile multiplies (weight fragments beyond a tile's own chunks are zero).
 // The workgroup has NW = NT R waves (<= MAXW).
-template <typename T, int EPI, int NTT, int NTQ, int SPAN, bool SPLIT, int MAXW>
-__global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 3 : (EPI == ZEPI_BWD ? 4 : 5)))) k_zt_epi(const float2 *__restrict__ u, T *__restrict__ out,
-                                                             const T *__restrict__ src, const T *__restrict__ gy,
-                                                             const float *__restrict__ wpw,
-                                                             const float *__restrict__ bpw, float *__restrict__ part,
-                                                             const typename OpOf<T>::type *__restrict__ tabZ,
-                                                             const typename OpOf<T>::type *__restrict__ tabZ_lo,
-                                                             const typename OpOf<T>::type *__restrict__ tabT,
-                                                             const typename OpOf<T>::type *__restrict__ tabT_lo,
-                                                             ZtArgs a)
+template <typename T, int EPI, int NTT, int NTQ, int SPAN, bool SPLIT>
+__device__ __forceinline__ void zt_epi_body(const float2 *__restrict__ u, T *__restrict__ out,
+                                            const T *__restrict__ src, const T *__restrict__ gy,
+                                            const float *__restrict__ wpw, const float *__restrict__ bpw,
+                                            float *__restrict__ part,
+                                            const typename OpOf<T>::type *__restrict__ tabZ,
+                                            const typename OpOf<T>::type *__restrict__ tabZ_lo,
+                                            const typename OpOf<T>::type *__restrict__ tabT,
+                                            const typename OpOf<T>::type *__restrict__ tabT_lo, const ZtArgs &a)
 {
     typedef typename OpOf<T>::type Op;
     constexpr bool PW = EPI != ZEPI_PLAIN;
@@ -98,7 +124,10 @@ __global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(
     const bool has_src = PW && Csrc > 0;
     const long long nxy = (long long)a.Nx * a.Ny, plane = (long long)Nz * Nt, ncell = nxy * plane;
 
-    const int ldv = 16 * NTT + 4;
+    // V rows hold 16 NTT values; the 4-value chunks of row r are stored XOR-swizzled by vswz(r)
+    // so that 16 consecutive rows read at one chunk position fall in distinct banks
+    constexpr int ldv = 16 * NTT;
+    auto vswz = [](int r) { return (r >> (sizeof(T) == 2 ? 2 : 1)) & 3; };
     T *ure = reinterpret_cast<T *>(smem);
     T *uim = ure + a.uim_off;
     T *vl = reinterpret_cast<T *>(smem + a.off_v);
@@ -157,23 +186,55 @@ __global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(
     const int u_r0 = u_one ? (int)threadIdx.x % KK : (int)threadIdx.x;
     const int u_c0 = u_one ? (int)threadIdx.x / KK : 0;
     const bool u_ok = u_one ? (int)threadIdx.x < u_cstep * KK : true;
-    // source staging: thread -> (zl, t4) pairs (4 consecutive t), channels strided by sp_cstep
-    const int nt4 = Nt / 4, npair = ZC * nt4;
-    const bool sp_one = npair <= NTH;
-    const int sp_cstep = sp_one ? NTH / npair : 1;
-    const bool sp_ok = sp_one ? (int)threadIdx.x < sp_cstep * npair : true;
-    const int sp_c0 = sp_one ? (int)threadIdx.x / npair : 0;
+    // source staging: item (pair (zl, t4), channel quad cq) loads 4 consecutive t of channels
+    // 4 cq .. 4 cq + 3, transposes them in registers and writes 4 rows t of 4 channels to LDS.
+    // Fast path (at most SQ items per thread): the items are loaded one chunk ahead, during the
+    // previous chunk's phase 2, and written at the top of the chunk.
+    constexpr int SQ = 1;
+    const int nt4 = Nt / 4, npair = ZC * nt4, nquad = (Csrc + 3) / 4, nitem = npair * nquad;
+    const bool sp_fast = FNO_ZT_PREFETCH && has_src && nitem <= SQ * NTH;
+    Op pre[SQ][4];
+    // chunk whose channel-0 element (zl = 0, t = 0) is `cb` into pre; `zmax` = z values left in it
+    auto prefetch = [&](const T *cb, int zmax) {
+#pragma unroll
+        for (int m = 0; m < SQ; m++) {
+            const int e = threadIdx.x + m * NTH, pr = e % npair, cq = e / npair;
+            const int zl = pr / nt4, t4 = pr - zl * nt4;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                const int ci = 4 * cq + k;
+                pre[m][k] = (e < nitem && zl < zmax && ci < Csrc)
+                                ? *reinterpret_cast<const Op *>(cb + (long long)zl * Nt + 4 * t4 + (long long)ci * ncell)
+                                : op_zero<T>();
+            }
+        }
+    };
+    // write item e's 4 x 4 block from v to LDS
+    auto put_item = [&](int e, const Op (&v)[4]) {
+        const int pr = e % npair, cq = e / npair, zl = pr / nt4, t4 = pr - zl * nt4;
+        Op r[4];
+        op_transpose4(v, r);
+        T *d = xt + (size_t)(4 * t4) * ldT + zl * Csp + 4 * cq;
+#pragma unroll
+        for (int jj = 0; jj < 4; jj++) *reinterpret_cast<Op *>(d + (size_t)jj * ldT) = r[jj];
+    };
     const int ngroups = ZC / ZG;
     const int QH = a.QZ / 2;
     __syncthreads();
 
     const long long nplanes = (long long)a.B * nxy;
+    auto plane_src = [&](long long pl) {
+        const long long bb = pl / nxy;
+        return src + bb * Csrc * ncell + (pl - bb * nxy) * plane;
+    };
+    if (sp_fast && (long long)blockIdx.x < nplanes) prefetch(plane_src(blockIdx.x), Nz);
     for (long long pl = blockIdx.x; pl < nplanes; pl += gridDim.x) {
         const int b = (int)(pl / nxy);
         const long long xy = pl % nxy;
         const T *srcp = src + (long long)b * Csrc * ncell + xy * plane;
-        // element offset of this lane's column (zr, co) at z = 0 and t = 4 g
-        const long long ecol = ((long long)b * Cs + co) * ncell + xy * plane + (long long)zr * Nt + 4 * g;
+        const T *srcn = pl + gridDim.x < nplanes ? plane_src(pl + gridDim.x) : srcp;  // next plane
+        // element offset of this lane's column (zr, co) at z = 0 and its first t = 4 NTQ g
+        const long long ecol = ((long long)b * Cs + co) * ncell + xy * plane + (long long)zr * Nt + 4 * NTQ * g;
         __syncthreads();  // previous plane's readers of U are done
         // ---- phase 0: U of every channel, to [c][kz / 4][kt][kz % 4]
         if (u_ok)
@@ -193,41 +254,42 @@ __global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(
             // early loads of the first tile's epilogue operand (gy, or the accumulated output)
             Op ext[NTQ];
             auto load_ext = [&](int z0, Op(&e)[NTQ]) {
+                const T *base = EPI == ZEPI_BWD ? gy : out;
+                const bool want = EPI == ZEPI_BWD || (EPI == ZEPI_ADJ && a.accumulate);
+                const bool zin = z0 < Nz && z0 + zr < Nz;
+                const long long ei = ecol + (long long)z0 * Nt;
 #pragma unroll
-                for (int mt = 0; mt < NTQ; mt++) {
-                    e[mt] = op_zero<T>();
-                    const bool ok = z0 < Nz && z0 + zr < Nz && 16 * mt + 4 * g < Nt;
-                    const long long ei = ecol + (long long)z0 * Nt + 16 * mt;
-                    if (EPI == ZEPI_BWD && ok) e[mt] = *reinterpret_cast<const Op *>(gy + ei);
-                    if (EPI == ZEPI_ADJ && ok && a.accumulate) e[mt] = *reinterpret_cast<const Op *>(out + ei);
+                for (int mt = 0; mt < NTQ; mt++) e[mt] = op_zero<T>();
+                bool whole = false;
+                if constexpr (NTQ == 2) {
+                    whole = want && zin && 8 * g + 8 <= Nt;
+                    if (whole) load8(base + ei, e[0], e[1]);
+                }
+                if (!whole) {
+#pragma unroll
+                    for (int mt = 0; mt < NTQ; mt++)
+                        if (want && zin && 4 * NTQ * g + 4 * mt < Nt)
+                            e[mt] = *reinterpret_cast<const Op *>(base + ei + 4 * mt);
                 }
             };
             if (EPI == ZEPI_BWD || EPI == ZEPI_ADJ) load_ext(zc0 + tr * ZG, ext);
-            // source chunk -> LDS transposed [t][(zl, ci)]: thread owns pair (zl, t4), strides over channels
-            if (has_src && sp_ok) {
-                for (int pr = sp_one ? (int)threadIdx.x % npair : (int)threadIdx.x; pr < npair;
-                     pr += (sp_one ? npair : NTH)) {
-                    const int zl = pr / nt4, t4 = pr - zl * nt4;
-                    const bool zin = zc0 + zl < Nz;
+            // source chunk -> LDS transposed [t][(zl, ci)]
+            if (sp_fast) {
+#pragma unroll
+                for (int m = 0; m < SQ; m++)
+                    if ((int)threadIdx.x + m * NTH < nitem) put_item(threadIdx.x + m * NTH, pre[m]);
+            } else if (has_src) {
+                for (int e = threadIdx.x; e < nitem; e += NTH) {
+                    const int pr = e % npair, cq = e / npair, zl = pr / nt4, t4 = pr - zl * nt4;
                     const T *sp = srcp + (long long)(zc0 + zl) * Nt + 4 * t4;
-                    T *dl = xt + (size_t)(4 * t4) * ldT + zl * Csp;
-                    for (int ci0 = sp_c0; ci0 < Csrc; ci0 += 4 * sp_cstep) {
-                        Op vv[4];
+                    Op v[4];
 #pragma unroll
-                        for (int k = 0; k < 4; k++) {
-                            const int ci = ci0 + k * sp_cstep;
-                            vv[k] = (zin && ci < Csrc) ? *reinterpret_cast<const Op *>(sp + (long long)ci * ncell)
-                                                       : op_zero<T>();
-                        }
-#pragma unroll
-                        for (int k = 0; k < 4; k++) {
-                            const int ci = ci0 + k * sp_cstep;
-                            if (ci < Csrc) {
-#pragma unroll
-                                for (int jj = 0; jj < 4; jj++) op_put(dl + (size_t)jj * ldT + ci, vv[k], jj);
-                            }
-                        }
+                    for (int k = 0; k < 4; k++) {
+                        const int ci = 4 * cq + k;
+                        v[k] = (zc0 + zl < Nz && ci < Csrc) ? *reinterpret_cast<const Op *>(sp + (long long)ci * ncell)
+                                                            : op_zero<T>();
                     }
+                    put_item(e, v);
                 }
             }
             // ---- phase 1: V^T tiles (channel cs, (re/im, kt) tile mt) of this z tile into LDS
@@ -258,9 +320,15 @@ __global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(
                 }
                 // acc[r] = V^T[(ri, kt) = 16 mt + 4 g + r][z = zc0 + c]
                 float v[4] = {acc[0], acc[1], acc[2], acc[3]};
-                store4(vl + ((size_t)c * Cs + cs) * ldv + 16 * mt + 4 * g, v);
+                const int vr = c * Cs + cs;
+                store4(vl + (size_t)vr * ldv + 16 * mt + 4 * (g ^ vswz(vr)), v);
             }
             __syncthreads();
+            // the next chunk's source: this plane's next chunk, else the next plane's first
+            if (sp_fast) {
+                if (zc0 + ZC < Nz) prefetch(srcp + (long long)(zc0 + ZC) * Nt, Nz - zc0 - ZC);
+                else prefetch(srcn, pl + gridDim.x < nplanes ? Nz : 0);
+            }
             // ---- phase 2: this wave's tile of groups tr, tr + R, ...
             for (int gi = tr; gi < ngroups; gi += R) {
                 const int z0 = zc0 + gi * ZG;
@@ -271,16 +339,17 @@ __global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(
                 const int vrow = gi * ZG * Cs + 16 * tj + c;
                 Op bv[NTT];
 #pragma unroll
-                for (int q = 0; q < NTT; q++) bv[q] = *reinterpret_cast<const Op *>(vl + (size_t)vrow * ldv + 16 * q + 4 * g);
-                // A[t = 16 mt + c][k = 16 (qlo + s) + 4 g + jj]
-                const T *xa = xt + (size_t)c * ldT + gi * ZG * Csp + 16 * qlo + 4 * g;
+                for (int q = 0; q < NTT; q++)
+                    bv[q] = *reinterpret_cast<const Op *>(vl + (size_t)vrow * ldv + 16 * q + 4 * (g ^ vswz(vrow)));
+                // A[t][k = 16 (qlo + s) + 4 g + jj] for row c of t tile mt: t = 4 NTQ (c / 4) + 4 mt + c % 4
+                const T *xa = xt + (size_t)(4 * NTQ * (c >> 2) + (c & 3)) * ldT + gi * ZG * Csp + 16 * qlo + 4 * g;
                 Op av[has_src_c<EPI>() ? SPAN : 1][NTQ];
                 if (PW) {
 #pragma unroll
                     for (int s = 0; s < SPAN; s++)
 #pragma unroll
                         for (int mt = 0; mt < NTQ; mt++)
-                            av[s][mt] = has_src ? *reinterpret_cast<const Op *>(xa + (size_t)16 * mt * ldT + 16 * s)
+                            av[s][mt] = has_src ? *reinterpret_cast<const Op *>(xa + (size_t)4 * mt * ldT + 16 * s)
                                                 : op_zero<T>();
                 }
                 f4v acc[NTQ];
@@ -297,41 +366,49 @@ __global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(
                         for (int s = 0; s < SPAN; s++) acc[mt] = mma16(av[s][mt], wd[s], acc[mt]);
                     }
                 }
-                // epilogue: acc[mt][r] is (t = 16 mt + 4 g + r, column n)
+                // epilogue: acc[mt][r] is (t = 4 NTQ g + 4 mt + r, column n)
                 const bool zok = z0 + zr < Nz;
+                float v[NTQ][4];
 #pragma unroll
                 for (int mt = 0; mt < NTQ; mt++) {
-                    {
-                        const bool ok = zok && 16 * mt + 4 * g < Nt;
-                        float v[4];
+                    const bool ok = zok && 4 * NTQ * g + 4 * mt < Nt;
 #pragma unroll
-                        for (int r = 0; r < 4; r++) v[r] = acc[mt][r];
-                        if (EPI == ZEPI_BLOCK) {
+                    for (int r = 0; r < 4; r++) v[mt][r] = acc[mt][r];
+                    if (EPI == ZEPI_BLOCK) {
 #pragma unroll
-                            for (int r = 0; r < 4; r++) v[r] = gelu_fast(v[r] + bj);
-                        } else if (EPI == ZEPI_BWD) {
+                        for (int r = 0; r < 4; r++) v[mt][r] = gelu_fast(v[mt][r] + bj);
+                    } else if (EPI == ZEPI_BWD) {
 #pragma unroll
-                            for (int r = 0; r < 4; r++) {
-                                v[r] = ok ? op_get(ext[mt], r) * gelu_grad_fast(v[r] + bj) : 0.f;
-                                gbacc += v[r];
-                            }
-                            acc[mt] = f4v{v[0], v[1], v[2], v[3]};  // gradient tile, B of the product below
-                        } else if (EPI == ZEPI_ADJ) {
-#pragma unroll
-                            for (int r = 0; r < 4; r++) v[r] += op_get(ext[mt], r);
+                        for (int r = 0; r < 4; r++) {
+                            v[mt][r] = ok ? op_get(ext[mt], r) * gelu_grad_fast(v[mt][r] + bj) : 0.f;
+                            gbacc += v[mt][r];
                         }
-                        if (ok) store4(out + ecol + (long long)z0 * Nt + 16 * mt, v);
+                        acc[mt] = f4v{v[mt][0], v[mt][1], v[mt][2], v[mt][3]};  // gradient tile, B of the product below
+                    } else if (EPI == ZEPI_ADJ) {
+#pragma unroll
+                        for (int r = 0; r < 4; r++) v[mt][r] += op_get(ext[mt], r);
                     }
+                }
+                T *op = out + ecol + (long long)z0 * Nt;
+                bool whole = false;
+                if constexpr (NTQ == 2) {
+                    whole = zok && 8 * g + 8 <= Nt;
+                    if (whole) store8(op, v);
+                }
+                if (!whole) {
+#pragma unroll
+                    for (int mt = 0; mt < NTQ; mt++)
+                        if (zok && 4 * NTQ * g + 4 * mt < Nt) store4(op + 4 * mt, v[mt]);
                 }
                 if (EPI == ZEPI_BWD) {
                     // C[(z', i) = 16 (qlo + s) + 4 g + r][n] += sum_t x[z'][i][t] gz[n][t]; K chunk = t tile mt
-                    const T *xg = xt + (size_t)(4 * g) * ldT + gi * ZG * Csp + 16 * qlo + c;
+                    const T *xg = xt + (size_t)(4 * NTQ * g) * ldT + gi * ZG * Csp + 16 * qlo + c;
 #pragma unroll
                     for (int mt = 0; mt < NTQ; mt++) {
                         const Op bg = to_op<T>(acc[mt]);
 #pragma unroll
                         for (int s = 0; s < NGW; s++) {
-                            const Op ax = op_gather(xg + (size_t)16 * mt * ldT + 16 * s, ldT);
+                            const Op ax = op_gather(xg + (size_t)4 * mt * ldT + 16 * s, ldT);
                             gwacc[s] = mma16(ax, bg, gwacc[s]);
                         }
                     }
@@ -382,6 +459,39 @@ __global__ void __launch_bounds__(64 * MAXW) __attribute__((amdgpu_waves_per_eu(
     }
 }
 
+
+// One kernel name per epilogue, so that traces and counters tell them apart.
+#define FNO_ZT_KERNEL(NAME, EPI)                                                                                  \
+    template <typename T, int NTT, int NTQ, int SPAN, bool SPLIT, int MAXW>                                        \
+    __global__ void __launch_bounds__(64 * MAXW)                                                                   \
+        __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? FNO_ZT_WAVES_F32                                      \
+                                                              : (EPI == ZEPI_BWD ? FNO_ZT_WAVES_BWD : FNO_ZT_WAVES_BF16)))) \
+        NAME(const float2 *__restrict__ u, T *__restrict__ out, const T *__restrict__ src, const T *__restrict__ gy, \
+             const float *__restrict__ wpw, const float *__restrict__ bpw, float *__restrict__ part,                \
+             const typename OpOf<T>::type *__restrict__ tabZ, const typename OpOf<T>::type *__restrict__ tabZ_lo,   \
+             const typename OpOf<T>::type *__restrict__ tabT, const typename OpOf<T>::type *__restrict__ tabT_lo,   \
+             ZtArgs a)                                                                                             \
+    {                                                                                                              \
+        zt_epi_body<T, EPI, NTT, NTQ, SPAN, SPLIT>(u, out, src, gy, wpw, bpw, part, tabZ, tabZ_lo, tabT, tabT_lo, a); \
+    }
+FNO_ZT_KERNEL(k_zt_plain, ZEPI_PLAIN)
+FNO_ZT_KERNEL(k_zt_block, ZEPI_BLOCK)
+FNO_ZT_KERNEL(k_zt_bwd, ZEPI_BWD)
+FNO_ZT_KERNEL(k_zt_adj, ZEPI_ADJ)
+#undef FNO_ZT_KERNEL
+
+template <int EPI, typename T, int NTT, int NTQ, int SPAN, bool SPLIT, int MAXW> struct ZtKernel;
+#define FNO_ZT_PICK(NAME, EPI)                                                                                    \
+    template <typename T, int NTT, int NTQ, int SPAN, bool SPLIT, int MAXW>                                        \
+    struct ZtKernel<EPI, T, NTT, NTQ, SPAN, SPLIT, MAXW> {                                                          \
+        static const void *get() { return reinterpret_cast<const void *>(NAME<T, NTT, NTQ, SPAN, SPLIT, MAXW>); }   \
+    };
+FNO_ZT_PICK(k_zt_plain, ZEPI_PLAIN)
+FNO_ZT_PICK(k_zt_block, ZEPI_BLOCK)
+FNO_ZT_PICK(k_zt_bwd, ZEPI_BWD)
+FNO_ZT_PICK(k_zt_adj, ZEPI_ADJ)
+#undef FNO_ZT_PICK
+
 // ---------------------------------------------------------------- launcher
 struct ZtTabs {
     const void *z, *z_lo, *t, *t_lo;
@@ -400,7 +510,13 @@ static int gcd_int(int a, int b)
 static size_t al16(size_t v) { return (v + 15) / 16 * 16; }
 
 // Geometry and LDS carve-up of one launch; returns the LDS bytes (0: shape not supported).
-static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, ZtArgs &a)
+static int zt_target_waves(int epi, int elem)
+{
+    if (elem == 4) return FNO_ZT_TARGET_F32;
+    return epi == ZEPI_BLOCK ? FNO_ZT_TARGET_BLOCK : epi == ZEPI_BWD ? FNO_ZT_TARGET_BWD : FNO_ZT_TARGET_ADJ;
+}
+
+static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, int target, ZtArgs &a)
 {
     a = ZtArgs{};
     a.B = d.B;
@@ -419,8 +535,8 @@ static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, ZtArgs &a)
     a.ZG = 16 / gcd_int(Cs, 16);
     a.NT = a.ZG * Cs / 16;
     if (a.NT > kZtMaxWaves) return 0;
-    // waves per tile index: about 8 waves in all (at most 16), never more than there are groups
-    a.R = std::max(1, std::min(16 / a.ZG, (8 + a.NT - 1) / a.NT));
+    // waves per tile index: about `target` waves in all (at most 16), never more than there are groups
+    a.R = std::max(1, std::min(16 / a.ZG, (target + a.NT - 1) / a.NT));
     while (a.NT * a.R > kZtMaxWaves) a.R--;
     int span = 1;
     for (int j = 0; j < a.NT && Csrc > 0; j++) {
@@ -429,17 +545,22 @@ static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, ZtArgs &a)
         span = std::max(span, qhi - qlo + 1);
     }
     if (span > kZtMaxSpan) return 0;
-    a.SPAN = Csrc == 0 ? 1 : (span <= 2 ? 2 : 4);
-    // row stride of the transposed source: every tile reads SPAN chunks from its first one, at
-    // most 15 Csp + 16 SPAN columns in; rows end with the over-read of the last group
-    a.ldT = (std::max(16 * a.Csp + 12, 15 * a.Csp + 16 * a.SPAN) + 3) / 4 * 4;
+    a.SPAN = Csrc == 0 ? 1 : std::max(2, span);
+    // row stride of the transposed source: every tile reads SPAN chunks from its first one, so
+    // the last group's tiles read up to 16 (qlo + SPAN) columns past that group's start
+    int reach = 16 * a.Csp;
+    for (int j = 0; j < a.NT && Csrc > 0; j++) {
+        const int qlo = ((16 * j) / Cs * a.Csp) / 16;
+        reach = std::max(reach, (16 - a.ZG) * a.Csp + 16 * (qlo + a.SPAN));
+    }
+    a.ldT = (reach + 3) / 4 * 4;
     const int ntt = d.K[3] <= 8 ? 1 : 2;
     // imaginary plane at a word offset = 16 (mod 32) from the real one
     a.uim_off = Cs * a.Kt * a.Kzp;
     while (((size_t)a.uim_off * elem / 4) % 32 != 16) a.uim_off += 16 / elem;
     size_t off = al16(((size_t)a.uim_off + (size_t)Cs * a.Kt * a.Kzp) * elem);
     a.off_v = (int)off;
-    off += al16((size_t)16 * Cs * (16 * ntt + 4) * elem);
+    off += al16((size_t)16 * Cs * (16 * ntt) * elem);
     a.off_x = (int)off;
     if (Csrc) off += al16((size_t)16 * a.NTQ * a.ldT * elem);
     // the BWD reduction at the end reuses the front: [waves][span][4][64] slots + [waves][64]
@@ -448,9 +569,12 @@ static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, ZtArgs &a)
 
 static bool zt_pair_ok(const Dims &d, int Cs, int Csrc, int elem)
 {
-    ZtArgs a;
-    const size_t lds = zt_layout(d, Cs, Csrc, elem, a);
-    return lds > 0 && lds <= 160 * 1024;
+    for (int epi = ZEPI_PLAIN; epi <= ZEPI_ADJ; epi++) {
+        ZtArgs a;
+        const size_t lds = zt_layout(d, Cs, Csrc, elem, zt_target_waves(epi, elem), a);
+        if (lds == 0 || lds > 160 * 1024) return false;
+    }
+    return true;
 }
 
 bool zt_supported(const Dims &d, int dtype)
@@ -474,26 +598,28 @@ static hipError_t launch_zt_t(const Dims &d, int Cs, int Csrc, int accumulate, c
     typedef typename OpOf<T>::type Op;
     constexpr bool split = sizeof(T) == 2;
     ZtArgs a;
-    const size_t lds = zt_layout(d, Cs, Csrc, sizeof(T), a);
+    const size_t lds = zt_layout(d, Cs, Csrc, sizeof(T), zt_target_waves(EPI, sizeof(T)), a);
     if (lds == 0) return hipErrorInvalidValue;
     a.accumulate = accumulate;
     const int nth = 64 * a.NT * a.R;
-    if (a.NT * a.R > MAXW || a.NTQ != NTQ || (EPI != ZEPI_PLAIN && a.SPAN > SPAN)) return hipErrorInvalidValue;
-    auto kern = k_zt_epi<T, EPI, NTT, NTQ, SPAN, split, MAXW>;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (a.NT * a.R > MAXW || a.NTQ != NTQ || (EPI != ZEPI_PLAIN && a.SPAN != SPAN && Csrc > 0))
+        return hipErrorInvalidValue;
+    const void *kern = ZtKernel<EPI, T, NTT, NTQ, SPAN, split, MAXW>::get();
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     // persistent grid: as many workgroups as can be resident at once (at most one per plane)
     int grid = zt_grid(d);
     int per_cu = 0, dev = 0, ncu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern), nth, lds) ==
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, nth, lds) ==
             hipSuccess &&
         hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && per_cu > 0)
         grid = std::min(grid, per_cu * ncu);
     if (rows_used) *rows_used = grid;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(nth), lds, st, u, out, src, gy, wpw, bpw, part, (const Op *)tb.z,
-                       (const Op *)tb.z_lo, (const Op *)tb.t, (const Op *)tb.t_lo, a);
+    const Op *tz = (const Op *)tb.z, *tzl = (const Op *)tb.z_lo, *tt = (const Op *)tb.t, *ttl = (const Op *)tb.t_lo;
+    void *args[] = {&u, &out, &src, &gy, &wpw, &bpw, &part, &tz, &tzl, &tt, &ttl, &a};
+    e = hipLaunchKernel(kern, dim3(grid), dim3(nth), args, lds, st);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
@@ -505,23 +631,27 @@ hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const float2 *u, 
                      int *rows_used)
 {
     ZtArgs a;
-    if (zt_layout(d, Cs, Csrc, sizeof(T), a) == 0) return hipErrorInvalidValue;
-    const bool w10 = a.NT * a.R <= 10;
-    const int sel = (d.K[3] <= 8 ? 0 : 4) + (a.NTQ == 1 ? 0 : 2) + (a.SPAN <= 2 ? 0 : 1);
+    if (zt_layout(d, Cs, Csrc, sizeof(T), zt_target_waves(epi, sizeof(T)), a) == 0) return hipErrorInvalidValue;
+    const bool w8 = a.NT * a.R <= 8;
+    const int sel = (d.K[3] <= 8 ? 0 : 6) + (a.NTQ == 1 ? 0 : 3) + std::min(2, std::max(0, a.SPAN - 2));
 #define FNO_ZT_W(E, NTT_, NTQ_, SPAN_)                                                                              \
-    return w10 ? launch_zt_t<T, E, NTT_, NTQ_, SPAN_, 10>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw, bpw, part, \
-                                                          tb, st, rows_used)                                        \
-               : launch_zt_t<T, E, NTT_, NTQ_, SPAN_, kZtMaxWaves>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw,   \
-                                                                   bpw, part, tb, st, rows_used)
+    return w8 ? launch_zt_t<T, E, NTT_, NTQ_, SPAN_, 8>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw, bpw, part,   \
+                                                        tb, st, rows_used)                                          \
+              : launch_zt_t<T, E, NTT_, NTQ_, SPAN_, kZtMaxWaves>(d, Cs, Csrc, accumulate, u, out, src, gy, wpw,    \
+                                                                  bpw, part, tb, st, rows_used)
 #define FNO_ZT(E)                                                                                                   \
-    switch (E == ZEPI_PLAIN ? sel & 6 : sel) {                                                                      \
+    switch (E == ZEPI_PLAIN ? sel - sel % 3 : sel) {                                                                \
     case 0: FNO_ZT_W(E, 1, 1, 2);                                                                                   \
-    case 1: FNO_ZT_W(E, 1, 1, 4);                                                                                   \
-    case 2: FNO_ZT_W(E, 1, 2, 2);                                                                                   \
-    case 3: FNO_ZT_W(E, 1, 2, 4);                                                                                   \
-    case 4: FNO_ZT_W(E, 2, 1, 2);                                                                                   \
-    case 5: FNO_ZT_W(E, 2, 1, 4);                                                                                   \
-    case 6: FNO_ZT_W(E, 2, 2, 2);                                                                                   \
+    case 1: FNO_ZT_W(E, 1, 1, 3);                                                                                   \
+    case 2: FNO_ZT_W(E, 1, 1, 4);                                                                                   \
+    case 3: FNO_ZT_W(E, 1, 2, 2);                                                                                   \
+    case 4: FNO_ZT_W(E, 1, 2, 3);                                                                                   \
+    case 5: FNO_ZT_W(E, 1, 2, 4);                                                                                   \
+    case 6: FNO_ZT_W(E, 2, 1, 2);                                                                                   \
+    case 7: FNO_ZT_W(E, 2, 1, 3);                                                                                   \
+    case 8: FNO_ZT_W(E, 2, 1, 4);                                                                                   \
+    case 9: FNO_ZT_W(E, 2, 2, 2);                                                                                   \
+    case 10: FNO_ZT_W(E, 2, 2, 3);                                                                                  \
     default: FNO_ZT_W(E, 2, 2, 4);                                                                                  \
     }
     switch (epi) {
