@@ -21,6 +21,8 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -112,6 +114,45 @@ def kernel_model(name, B, Ci, Co, grid, modes, act_bytes):
         return None
     by, fl = models[name]
     return dict(bytes=by, flops=fl)
+
+
+# ------------------------------------------------------------------ measured HBM traffic
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "paper_2211_12709_amd", "csrc")
+# sources whose text decides a kernel's memory traffic (a counter figure is stale once they change)
+KERNEL_SOURCES = {
+    "zt": ["zt_epi.hip", "tables.hip", "mfma_common.h", "fno_internal.h"],
+    "tzy": ["fwd_tzy.hip", "tables.hip", "mfma_common.h", "fno_internal.h"],
+}
+
+
+def source_hash(label):
+    key = "zt" if label.startswith("zt_") else "tzy" if label.startswith("tzy") else None
+    if key is None:
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[key]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(label, dtype, workload):
+    """HBM bytes per launch of kernel `label` from the committed rocprofv3 counter summaries
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain-copy calibration), or None when there is no
+    figure for this kernel, dtype and workload or its sources changed since it was taken."""
+    want = source_hash(label)
+    if want is None:
+        return None
+    for path in sorted(glob.glob(os.path.join(HERE, "profiles", "*hbm_counters*.txt"))):
+        with open(path) as fh:
+            for line in fh:
+                f = line.split()
+                if len(f) == 6 and f[0] == "traffic" and f[1] == label and f[2] == dtype and f[3] == workload:
+                    kv = dict(x.split("=", 1) for x in f[4:])
+                    if kv.get("src") == want:
+                        return int(kv["bytes"])
+    return None
 
 
 # ------------------------------------------------------------------ helpers
@@ -259,7 +300,8 @@ def main():
         if t_hbm >= t_mfma:
             ach = km["bytes"] / (avg_ms * 1e-3) / 1e9
             roof = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                        traffic=None, kernel=name, avg_ms=avg_ms, bytes_per_launch=km["bytes"])
+                        traffic=profiled_traffic(name, "bf16", args.workload), kernel=name, avg_ms=avg_ms,
+                        bytes_per_launch=km["bytes"])
         else:
             ach = km["flops"] / (avg_ms * 1e-3) / 1e12
             roof = dict(bound="mfma", achieved=ach, peak=MFMA_PEAK_TFLOPS["bf16"], unit="TFLOP/s",
