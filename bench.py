@@ -88,6 +88,7 @@ def kernel_model(name, B, Ci, Co, grid, modes, act_bytes):
     A = B * C * N * act_bytes                                # one activation tensor
     kx, ky, kz = 2 * mx, 2 * my, 2 * mz
     t1 = B * C * nx * ny * kz * mt * 8                       # t,z spectrum, complex64
+    u1 = B * C * nx * ny * kz * mt * 2 * act_bytes           # its y-inverse as the z,t kernels read it
     t2 = B * C * nx * ky * kz * mt * 8                       # t,z,y spectrum
     sp = B * C * kx * ky * kz * mt * 8                       # retained spectrum
     W = Ci * Co * kx * ky * kz * mt * 8
@@ -99,13 +100,13 @@ def kernel_model(name, B, Ci, Co, grid, modes, act_bytes):
     models = {
         "tzy_fwd<bf16>": (B * C * N * 2 + t2, t_fl + z_fl + y_fl),
         "tzy_fwd<f32>": (B * C * N * 4 + t2, t_fl + z_fl + y_fl),
-        "zt_plain": (t1 + A, t_fl + z_fl),
-        "zt_block": (t1 + 2 * A, t_fl + z_fl + pw),
-        "zt_bwd": (t1 + 3 * A, t_fl + z_fl + 2 * pw),
-        "zt_adj": (t1 + 2 * A, t_fl + z_fl + pw),
+        "zt_plain": (u1 + A, t_fl + z_fl),
+        "zt_block": (u1 + 2 * A, t_fl + z_fl + pw),
+        "zt_bwd": (u1 + 3 * A, t_fl + z_fl + 2 * pw),
+        "zt_adj": (u1 + 2 * A, t_fl + z_fl + pw),
         "axis_fwd_x": (t2 + sp, x_fl),
         "axis_inv_x": (sp + t2, x_fl),
-        "axis_inv_y": (t2 + t1, y_fl),
+        "axis_inv_y": (t2 + u1, y_fl),
         "axis_fwd_y": (t1 + t2, y_fl),
         "mix_fwd": (2 * sp + W, 8 * B * Ci * Co * kx * ky * kz * mt),
         "mix_bwd": (3 * sp + 2 * W, 16 * B * Ci * Co * kx * ky * kz * mt),

@@ -50,13 +50,13 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3 };
 bool zt_supported(const Dims &d, int dtype);
 int zt_grid(const Dims &d);
 template <typename T>
-hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const float2 *u, T *out, const T *src, const T *gy,
+hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const void *u, T *out, const T *src, const T *gy,
                      const float *wpw, const float *bpw, float *part, const ZtTabs &tb, int accumulate, hipStream_t st,
                      int *rows_used = nullptr);
 int zt_partial_rows(const Dims &d);
 template <typename TC>
-hipError_t launch_axis_mfma(const float2 *in, float2 *out, const void *tab, const void *tab_lo, long long outer,
-                            int Nin, int Nout, long long cols, hipStream_t st);
+hipError_t launch_axis_mfma(const float2 *in, void *out, const void *tab, const void *tab_lo, long long outer,
+                            int Nin, int Nout, long long cols, hipStream_t st, bool out16 = false);
 size_t axis_lds_bytes(int Ninp, int elem);
 TabGeom *new_axis_geom(const Dims &d, int a, bool forward);
 void launch_pw_reduce(const float *part, float *gwpw, float *gb, int Ci, int Co, int nchunk, int accumulate,
@@ -217,13 +217,18 @@ static int finish()
 // X^ of activations `in` (C channels) into xh, using t1/t2 as scratch.
 // One-axis contraction of complex spectra along axis ax (0 = x, 1 = y) on the
 // matrix cores (float operands): in [outer][Nin][cols] -> out [outer][Nout][cols].
+// bf16: bfloat16 operands (spectrum rounded once, basis as a hi + lo pair) with float
+// accumulation, result stored as bfloat16 (re, im) pairs -- used where the consumer
+// rounds it to bfloat16 anyway (the z,t synthesis of the bfloat16 path).
 static void axis_stage(const fno_plan_t *p, int ax, bool forward, const float2 *in, float2 *out, long long outer,
-                       long long cols, hipStream_t st, const char *name)
+                       long long cols, hipStream_t st, const char *name, bool bf16 = false)
 {
     const Dims &d = p->d;
     const int Nin = forward ? d.N[ax] : d.K[ax], Nout = forward ? d.K[ax] : d.N[ax];
     const Tables::Frag &tb = forward ? p->tab.ax_fwd[ax] : p->tab.ax_inv[ax];
-    if (axis_lds_bytes((Nin + 15) / 16 * 16, 4) <= 160 * 1024) {
+    if (bf16 && axis_lds_bytes((Nin + 15) / 16 * 16, 2) <= 160 * 1024) {
+        FNO_TIMED(p, st, name, note(launch_axis_mfma<__bf16>(in, out, tb.hi, tb.lo, outer, Nin, Nout, cols, st, true)));
+    } else if (axis_lds_bytes((Nin + 15) / 16 * 16, 4) <= 160 * 1024) {
         FNO_TIMED(p, st, name, note(launch_axis_mfma<float>(in, out, tb.f, nullptr, outer, Nin, Nout, cols, st)));
     } else {
         FNO_TIMED(p, st, name, launch_axis(in, out, p->tab.cs[ax], outer, Nin, Nout, cols, d.N[ax], forward ? 0 : 1, st));
@@ -277,7 +282,9 @@ static void inverse_xy(const fno_plan_t *p, const float2 *spec, int C, float2 *u
 {
     const Dims &d = p->d;
     if (!skip_x) axis_stage(p, 0, false, spec, u2, (long long)d.B * C, d.P, st, "axis_inv_x");
-    axis_stage(p, 1, false, u2, u1, (long long)d.B * C * d.N[0], d.kplane, st, "axis_inv_y");
+    // the y inverse feeds the z,t synthesis, which rounds it to the activation type
+    axis_stage(p, 1, false, u2, u1, (long long)d.B * C * d.N[0], d.kplane, st, "axis_inv_y",
+               p->desc.dtype == FNO_BF16 && zt_supported(d, FNO_BF16));
 }
 
 template <typename T>

@@ -7,7 +7,8 @@
 // Real form: rows (re/im, j), K = (re/im', n):
 //   forward  E = exp(-i theta): [[cos, sin], [-sin, cos]]
 //   inverse  E = exp(+i theta): [[cos, -sin], [sin, cos]]
-// The basis lives in a fragment-ordered table (tables.hip).  One workgroup
+// The basis lives in a fragment-ordered table (tables.hip).  OUT16 stores the
+// result as bfloat16 (re, im) pairs for a consumer that works in bfloat16.  One workgroup
 // owns an (o, 64-column) block: it stages in[o][*][cols] in LDS transposed to
 // [col][(re/im', n)] so that every lane's 4 K values are one vector read, and
 // each wave computes one 16-column tile for all row tiles.
@@ -25,8 +26,8 @@ struct AxisArgs {
     int QK;           // K chunks: 2 Ninp / 16
 };
 
-template <typename TC>
-__global__ void __launch_bounds__(256) k_axis_mfma(const float2 *__restrict__ in, float2 *__restrict__ out,
+template <typename TC, bool OUT16>
+__global__ void __launch_bounds__(256) k_axis_mfma(const float2 *__restrict__ in, void *__restrict__ out_,
                                                    const typename OpOf<TC>::type *__restrict__ tab,
                                                    const typename OpOf<TC>::type *__restrict__ tab_lo, AxisArgs a)
 {
@@ -51,7 +52,8 @@ __global__ void __launch_bounds__(256) k_axis_mfma(const float2 *__restrict__ in
     __syncthreads();
     const int cl = 16 * w + c;  // this wave's column tile, lane column
     const long long col = col0 + cl;
-    float2 *dst = out + o * a.Nout * a.cols;
+    float2 *dst = reinterpret_cast<float2 *>(out_) + o * a.Nout * a.cols;
+    s2v *dst16 = reinterpret_cast<s2v *>(out_) + o * a.Nout * a.cols;
     const int half = a.MT / 2;
     for (int mp = 0; mp < half; mp++) {
         // row tiles mp (re rows) and mp + half (im rows)
@@ -69,7 +71,12 @@ __global__ void __launch_bounds__(256) k_axis_mfma(const float2 *__restrict__ in
 #pragma unroll
         for (int r = 0; r < 4; r++) {
             const int j = 16 * mp + 4 * g + r;
-            if (j < a.Nout && col < a.cols) dst[(long long)j * a.cols + col] = make_float2(accr[r], acci[r]);
+            if (j < a.Nout && col < a.cols) {
+                if (OUT16)
+                    dst16[(long long)j * a.cols + col] = s2v{bf16_bits(accr[r]), bf16_bits(acci[r])};
+                else
+                    dst[(long long)j * a.cols + col] = make_float2(accr[r], acci[r]);
+            }
         }
     }
 }
@@ -77,8 +84,8 @@ __global__ void __launch_bounds__(256) k_axis_mfma(const float2 *__restrict__ in
 size_t axis_lds_bytes(int Ninp, int elem) { return (size_t)64 * (2 * Ninp + 4) * elem; }
 
 template <typename TC>
-hipError_t launch_axis_mfma(const float2 *in, float2 *out, const void *tab, const void *tab_lo, long long outer,
-                            int Nin, int Nout, long long cols, hipStream_t st)
+hipError_t launch_axis_mfma(const float2 *in, void *out, const void *tab, const void *tab_lo, long long outer,
+                            int Nin, int Nout, long long cols, hipStream_t st, bool out16)
 {
     typedef typename OpOf<TC>::type Op;
     AxisArgs a;
@@ -91,7 +98,7 @@ hipError_t launch_axis_mfma(const float2 *in, float2 *out, const void *tab, cons
     a.MT = 2 * a.Noutp / 16;
     a.QK = 2 * a.Ninp / 16;
     const size_t lds = axis_lds_bytes(a.Ninp, sizeof(TC));
-    auto kern = k_axis_mfma<TC>;
+    auto kern = out16 ? k_axis_mfma<TC, true> : k_axis_mfma<TC, false>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -101,9 +108,9 @@ hipError_t launch_axis_mfma(const float2 *in, float2 *out, const void *tab, cons
     return hipGetLastError();
 }
 
-template hipError_t launch_axis_mfma<float>(const float2 *, float2 *, const void *, const void *, long long, int, int,
-                                            long long, hipStream_t);
-template hipError_t launch_axis_mfma<__bf16>(const float2 *, float2 *, const void *, const void *, long long, int, int,
-                                             long long, hipStream_t);
+template hipError_t launch_axis_mfma<float>(const float2 *, void *, const void *, const void *, long long, int, int,
+                                            long long, hipStream_t, bool);
+template hipError_t launch_axis_mfma<__bf16>(const float2 *, void *, const void *, const void *, long long, int, int,
+                                             long long, hipStream_t, bool);
 
 }  // namespace fno

@@ -20,6 +20,14 @@ namespace fno {
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef short s4v __attribute__((ext_vector_type(4)));
 
+typedef short s2v __attribute__((ext_vector_type(2)));
+
+// Element type of an intermediate complex spectrum handed to a kernel working in type T:
+// (re, im) float for float, (re, im) bfloat16 bits for bfloat16.
+template <typename T> struct CplxOf;
+template <> struct CplxOf<float> { typedef float2 type; };
+template <> struct CplxOf<__bf16> { typedef s2v type; };
+
 // Operand fragment type of the MFMA for activation/compute type T.
 template <typename T> struct OpOf;
 template <> struct OpOf<float> { typedef f4v type; };

@@ -40,7 +40,7 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3 };
 #define FNO_ZT_WAVES_BF16 5  // waves per SIMD the bfloat16 BLOCK/ADJ/PLAIN kernels are compiled for
 #endif
 #ifndef FNO_ZT_WAVES_BWD
-#define FNO_ZT_WAVES_BWD 4  // the same for the bfloat16 BWD kernel
+#define FNO_ZT_WAVES_BWD 5  // the same for the bfloat16 BWD kernel
 #endif
 #ifndef FNO_ZT_WAVES_F32
 #define FNO_ZT_WAVES_F32 3  // the same for every float kernel
@@ -50,7 +50,7 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3 };
 #define FNO_ZT_TARGET_BLOCK 8
 #endif
 #ifndef FNO_ZT_TARGET_BWD
-#define FNO_ZT_TARGET_BWD 8
+#define FNO_ZT_TARGET_BWD 4
 #endif
 #ifndef FNO_ZT_TARGET_ADJ
 #define FNO_ZT_TARGET_ADJ 4  // also PLAIN
@@ -87,6 +87,18 @@ __device__ __forceinline__ s4v op_sign(s4v v, bool neg)
     return s4v{(short)(v[0] ^ m), (short)(v[1] ^ m), (short)(v[2] ^ m), (short)(v[3] ^ m)};
 }
 
+// (re, im) of an intermediate spectrum element into two LDS slots of type T (bits unchanged for bfloat16).
+__device__ __forceinline__ void cplx_put(float *re, float *im, float2 v)
+{
+    *re = v.x;
+    *im = v.y;
+}
+__device__ __forceinline__ void cplx_put(__bf16 *re, __bf16 *im, s2v v)
+{
+    *reinterpret_cast<short *>(re) = v[0];
+    *reinterpret_cast<short *>(im) = v[1];
+}
+
 // Operand fragment from four scalars of storage type T, `stride` elements apart (bits unchanged).
 __device__ __forceinline__ f4v op_gather(const float *p, int stride)
 {
@@ -104,7 +116,7 @@ template <int EPI> constexpr bool has_src_c() { return EPI != ZEPI_PLAIN; }
 // SPAN: source K chunks every tile multiplies (weight fragments beyond a tile's own chunks are zero).
 // The workgroup has NW = NT R waves (<= MAXW).
 template <typename T, int EPI, int NTT, int NTQ, int SPAN, bool SPLIT>
-__device__ __forceinline__ void zt_epi_body(const float2 *__restrict__ u, T *__restrict__ out,
+__device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__restrict__ u, T *__restrict__ out,
                                             const T *__restrict__ src, const T *__restrict__ gy,
                                             const float *__restrict__ wpw, const float *__restrict__ bpw,
                                             float *__restrict__ part,
@@ -240,13 +252,12 @@ __device__ __forceinline__ void zt_epi_body(const float2 *__restrict__ u, T *__r
         if (u_ok)
             for (int r = u_r0; r < KK; r += (u_one ? KK : NTH)) {
                 const int kz = r / Kt, kt = r - kz * Kt;
-                const float2 *up = u + ((long long)b * Cs * nxy + xy) * KK + r;
+                const typename CplxOf<T>::type *up = u + ((long long)b * Cs * nxy + xy) * KK + r;
                 const size_t ul = ((size_t)(kz >> 2) * Kt + kt) * 4 + (kz & 3);
                 T *ur = ure + ul, *ui = uim + ul;
                 for (int cs = u_c0; cs < Cs; cs += u_cstep) {
-                    const float2 v = up[(long long)cs * nxy * KK];
-                    ur[(size_t)cs * Kt * Kzp] = from_f32<T>(v.x);
-                    ui[(size_t)cs * Kt * Kzp] = from_f32<T>(v.y);
+                    const typename CplxOf<T>::type v = up[(long long)cs * nxy * KK];
+                    cplx_put(ur + (size_t)cs * Kt * Kzp, ui + (size_t)cs * Kt * Kzp, v);
                 }
             }
         for (int zc0 = 0; zc0 < Nz; zc0 += ZC) {
@@ -466,7 +477,8 @@ __device__ __forceinline__ void zt_epi_body(const float2 *__restrict__ u, T *__r
     __global__ void __launch_bounds__(64 * MAXW)                                                                   \
         __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? FNO_ZT_WAVES_F32                                      \
                                                               : (EPI == ZEPI_BWD ? FNO_ZT_WAVES_BWD : FNO_ZT_WAVES_BF16)))) \
-        NAME(const float2 *__restrict__ u, T *__restrict__ out, const T *__restrict__ src, const T *__restrict__ gy, \
+        NAME(const typename CplxOf<T>::type *__restrict__ u, T *__restrict__ out, const T *__restrict__ src,       \
+             const T *__restrict__ gy,                                                                             \
              const float *__restrict__ wpw, const float *__restrict__ bpw, float *__restrict__ part,                \
              const typename OpOf<T>::type *__restrict__ tabZ, const typename OpOf<T>::type *__restrict__ tabZ_lo,   \
              const typename OpOf<T>::type *__restrict__ tabT, const typename OpOf<T>::type *__restrict__ tabT_lo,   \
@@ -591,7 +603,7 @@ int zt_grid(const Dims &d) { return (int)std::min<long long>((long long)d.B * d.
 int zt_partial_rows(const Dims &d) { return zt_grid(d); }
 
 template <typename T, int EPI, int NTT, int NTQ, int SPAN, int MAXW>
-static hipError_t launch_zt_t(const Dims &d, int Cs, int Csrc, int accumulate, const float2 *u, T *out,
+static hipError_t launch_zt_t(const Dims &d, int Cs, int Csrc, int accumulate, const void *u_, T *out,
                               const T *src, const T *gy, const float *wpw, const float *bpw, float *part,
                               const ZtTabs &tb, hipStream_t st, int *rows_used)
 {
@@ -617,6 +629,7 @@ static hipError_t launch_zt_t(const Dims &d, int Cs, int Csrc, int accumulate, c
         grid = std::min(grid, per_cu * ncu);
     if (rows_used) *rows_used = grid;
     const Op *tz = (const Op *)tb.z, *tzl = (const Op *)tb.z_lo, *tt = (const Op *)tb.t, *ttl = (const Op *)tb.t_lo;
+    const typename CplxOf<T>::type *u = reinterpret_cast<const typename CplxOf<T>::type *>(u_);
     void *args[] = {&u, &out, &src, &gy, &wpw, &bpw, &part, &tz, &tzl, &tt, &ttl, &a};
     e = hipLaunchKernel(kern, dim3(grid), dim3(nth), args, lds, st);
     if (e != hipSuccess) return e;
@@ -624,9 +637,10 @@ static hipError_t launch_zt_t(const Dims &d, int Cs, int Csrc, int accumulate, c
 }
 
 // epi: ZEPI_*; Cs = output/spectral channels, Csrc = pointwise source channels.
+// u: the y-inverse spectrum [B Cs][Nx][Ny][Kz Kt] of CplxOf<T> elements (bfloat16 pairs for T = bf16).
 // rows_used (nullable) receives the number of BWD partial-sum rows written.
 template <typename T>
-hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const float2 *u, T *out, const T *src, const T *gy,
+hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const void *u, T *out, const T *src, const T *gy,
                      const float *wpw, const float *bpw, float *part, const ZtTabs &tb, int accumulate, hipStream_t st,
                      int *rows_used)
 {
@@ -664,10 +678,10 @@ hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const float2 *u, 
 #undef FNO_ZT
 }
 
-template hipError_t launch_zt<float>(int, const Dims &, int, int, const float2 *, float *, const float *,
+template hipError_t launch_zt<float>(int, const Dims &, int, int, const void *, float *, const float *,
                                      const float *, const float *, const float *, float *, const ZtTabs &, int,
                                      hipStream_t, int *);
-template hipError_t launch_zt<__bf16>(int, const Dims &, int, int, const float2 *, __bf16 *, const __bf16 *,
+template hipError_t launch_zt<__bf16>(int, const Dims &, int, int, const void *, __bf16 *, const __bf16 *,
                                       const __bf16 *, const float *, const float *, float *, const ZtTabs &, int,
                                       hipStream_t, int *);
 
