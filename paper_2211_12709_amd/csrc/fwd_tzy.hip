@@ -17,6 +17,16 @@
 #include "fno_internal.h"
 #include "mfma_common.h"
 
+#ifndef FNO_TZY_DEPTH
+#define FNO_TZY_DEPTH 2  // y planes whose loads are in flight per wave (even)
+#endif
+#ifndef FNO_TZY_WAVES_BF16
+#define FNO_TZY_WAVES_BF16 2  // waves per SIMD the bfloat16 kernel is compiled for
+#endif
+#ifndef FNO_TZY_WAVES_F32
+#define FNO_TZY_WAVES_F32 1  // the same for the float kernel
+#endif
+
 namespace fno {
 
 struct TzyArgs {
@@ -28,7 +38,7 @@ struct TzyArgs {
 // MY: row tiles of the y step (2 ceil(Ky/16)); NBW: its column tiles per wave.
 // NZBM: max z blocks (Nz <= 16*NZBM); MAXKB: max kz blocks.
 template <typename T, int NTT, bool SPLIT, int MY, int NBW, int NZBM, int MAXKB>
-__global__ void __launch_bounds__(256) k_tzy_fwd(const T *__restrict__ x, float2 *__restrict__ t2,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 2 ? FNO_TZY_WAVES_BF16 : FNO_TZY_WAVES_F32))) k_tzy_fwd(const T *__restrict__ x, float2 *__restrict__ t2,
                                                  const typename OpOf<T>::type *__restrict__ tabT,
                                                  const typename OpOf<T>::type *__restrict__ tabT_lo,
                                                  const typename OpOf<T>::type *__restrict__ tabZ,
@@ -212,7 +222,7 @@ __global__ void __launch_bounds__(256) k_tzy_fwd(const T *__restrict__ x, float2
     };
 
     // rotating register buffers: DEPTH planes are in flight while a pair is processed
-    constexpr int DEPTH = sizeof(T) == 2 ? 4 : 2;
+    constexpr int DEPTH = FNO_TZY_DEPTH;
     Op xb[DEPTH][NZBM][2];
 #pragma unroll
     for (int k = 0; k < DEPTH; k++) load_plane(plane_y(k), xb[k]);
