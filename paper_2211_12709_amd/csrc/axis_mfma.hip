@@ -24,6 +24,7 @@ struct AxisArgs {
     long long cols;   // columns (complex) per row
     int MT;           // row tiles: 2 Noutp / 16
     int QK;           // K chunks: 2 Ninp / 16
+    int CB;           // columns per workgroup (k_axis_syn)
 };
 
 template <typename TC, bool OUT16>
@@ -81,7 +82,94 @@ __global__ void __launch_bounds__(256) k_axis_mfma(const float2 *__restrict__ in
     }
 }
 
-size_t axis_lds_bytes(int Ninp, int elem) { return (size_t)64 * (2 * Ninp + 4) * elem; }
+// Synthesis-shaped contractions (short K = 2 Nin <= 16 QKM, long output): each wave keeps
+// the basis fragments of up to MPW row pairs (re rows mp, im rows mp + MT/2) in registers and
+// runs them over every 16-column tile of the workgroup's column block, so the table is read
+// once per wave instead of once per tile.  One workgroup owns (o, CB <= 256 columns).
+template <typename TC, bool OUT16, int QKM, int MPW>
+__global__ void __launch_bounds__(256) k_axis_syn(const float2 *__restrict__ in, void *__restrict__ out_,
+                                                  const typename OpOf<TC>::type *__restrict__ tab,
+                                                  const typename OpOf<TC>::type *__restrict__ tab_lo, AxisArgs a)
+{
+    typedef typename OpOf<TC>::type Op;
+    constexpr bool SPLIT = sizeof(TC) == 2;
+    const int CB = a.CB;
+    extern __shared__ __attribute__((aligned(16))) char smem[];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+    const long long nchunk = (a.cols + CB - 1) / CB;
+    const long long o = blockIdx.x / nchunk;
+    const long long col0 = (blockIdx.x % nchunk) * CB;
+    const int ldk = 2 * a.Ninp + 4;
+    TC *sl = reinterpret_cast<TC *>(smem);  // [CB cols][(re/im, n)]
+    const float2 *src = in + o * a.Nin * a.cols;
+    // stage: consecutive threads read consecutive columns of one row n
+    for (int e = threadIdx.x; e < a.Ninp * CB; e += 256) {
+        const int n = e / CB, cl = e % CB;
+        float2 v = make_float2(0.f, 0.f);
+        if (n < a.Nin && col0 + cl < a.cols) v = src[(long long)n * a.cols + col0 + cl];
+        sl[cl * ldk + n] = from_f32<TC>(v.x);
+        sl[cl * ldk + a.Ninp + n] = from_f32<TC>(v.y);
+    }
+    __syncthreads();
+    float2 *dst = reinterpret_cast<float2 *>(out_) + o * a.Nout * a.cols;
+    s2v *dst16 = reinterpret_cast<s2v *>(out_) + o * a.Nout * a.cols;
+    const int half = a.MT / 2;
+    const int ntile = (int)((std::min<long long>(CB, a.cols - col0) + 15) / 16);
+    for (int mp0 = w * MPW; mp0 < half; mp0 += 4 * MPW) {
+        Op ar[MPW][QKM], ai[MPW][QKM], arl[MPW][QKM], ail[MPW][QKM];
+#pragma unroll
+        for (int u = 0; u < MPW; u++)
+#pragma unroll
+            for (int q = 0; q < QKM; q++) {
+                const int mp = mp0 + u;
+                const bool ok = mp < half && q < a.QK;
+                const int ir = (mp * a.QK + q) * 64 + lane, ii = ((mp + half) * a.QK + q) * 64 + lane;
+                ar[u][q] = ok ? tab[ir] : op_zero<TC>();
+                ai[u][q] = ok ? tab[ii] : op_zero<TC>();
+                if (SPLIT) {
+                    arl[u][q] = ok ? tab_lo[ir] : op_zero<TC>();
+                    ail[u][q] = ok ? tab_lo[ii] : op_zero<TC>();
+                }
+            }
+        for (int ct = 0; ct < ntile; ct++) {
+            const int cl = 16 * ct + c;
+            const long long col = col0 + cl;
+            Op bv[QKM];
+#pragma unroll
+            for (int q = 0; q < QKM; q++)
+                bv[q] = q < a.QK ? *reinterpret_cast<const Op *>(sl + cl * ldk + 16 * q + 4 * g) : op_zero<TC>();
+#pragma unroll
+            for (int u = 0; u < MPW; u++) {
+                const int mp = mp0 + u;
+                if (mp < half) {
+                    f4v accr = f4_zero(), acci = f4_zero();
+#pragma unroll
+                    for (int q = 0; q < QKM; q++) {
+                        accr = mma16(ar[u][q], bv[q], accr);
+                        acci = mma16(ai[u][q], bv[q], acci);
+                        if (SPLIT) {
+                            accr = mma16(arl[u][q], bv[q], accr);
+                            acci = mma16(ail[u][q], bv[q], acci);
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int j = 16 * mp + 4 * g + r;
+                        if (j < a.Nout && col < a.cols) {
+                            if (OUT16)
+                                dst16[(long long)j * a.cols + col] = s2v{bf16_bits(accr[r]), bf16_bits(acci[r])};
+                            else
+                                dst[(long long)j * a.cols + col] = make_float2(accr[r], acci[r]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// LDS of the launch for a contraction of Ninp (padded) input rows (the larger of the two kernels).
+size_t axis_lds_bytes(int Ninp, int elem) { return (size_t)(2 * Ninp / 16 <= 8 ? 256 : 64) * (2 * Ninp + 4) * elem; }
 
 template <typename TC>
 hipError_t launch_axis_mfma(const float2 *in, void *out, const void *tab, const void *tab_lo, long long outer,
@@ -97,6 +185,21 @@ hipError_t launch_axis_mfma(const float2 *in, void *out, const void *tab, const 
     a.cols = cols;
     a.MT = 2 * a.Noutp / 16;
     a.QK = 2 * a.Ninp / 16;
+    if (a.QK <= 8) {
+        // widest column block that still gives at least 1024 workgroups (4 per CU)
+        a.CB = 256;
+        while (a.CB > 64 && outer * ((cols + a.CB - 1) / a.CB) < 1024) a.CB /= 2;
+        const size_t lds = (size_t)a.CB * (2 * a.Ninp + 4) * sizeof(TC);
+        auto kern = a.QK <= 4 ? (out16 ? k_axis_syn<TC, true, 4, 2> : k_axis_syn<TC, false, 4, 2>)
+                              : (out16 ? k_axis_syn<TC, true, 8, 1> : k_axis_syn<TC, false, 8, 1>);
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        const long long blocks = outer * ((cols + a.CB - 1) / a.CB);
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), lds, st, in, out, (const Op *)tab,
+                           (const Op *)tab_lo, a);
+        return hipGetLastError();
+    }
     const size_t lds = axis_lds_bytes(a.Ninp, sizeof(TC));
     auto kern = out16 ? k_axis_mfma<TC, true> : k_axis_mfma<TC, false>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
