@@ -36,8 +36,11 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3 };
 #ifndef FNO_ZT_PREFETCH
 #define FNO_ZT_PREFETCH 0  // load the next z chunk's source during the current chunk's phase 2
 #endif
-#ifndef FNO_ZT_WAVES_BF16
-#define FNO_ZT_WAVES_BF16 5  // waves per SIMD the bfloat16 BLOCK/ADJ/PLAIN kernels are compiled for
+#ifndef FNO_ZT_WAVES_BLOCK
+#define FNO_ZT_WAVES_BLOCK 6  // waves per SIMD the bfloat16 BLOCK kernel is compiled for
+#endif
+#ifndef FNO_ZT_WAVES_ADJ
+#define FNO_ZT_WAVES_ADJ 5  // the same for the bfloat16 ADJ and PLAIN kernels
 #endif
 #ifndef FNO_ZT_WAVES_BWD
 #define FNO_ZT_WAVES_BWD 5  // the same for the bfloat16 BWD kernel
@@ -47,7 +50,7 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3 };
 #endif
 // waves per workgroup aimed at (rounded to a multiple of the tile count), per epilogue
 #ifndef FNO_ZT_TARGET_BLOCK
-#define FNO_ZT_TARGET_BLOCK 8
+#define FNO_ZT_TARGET_BLOCK 4
 #endif
 #ifndef FNO_ZT_TARGET_BWD
 #define FNO_ZT_TARGET_BWD 4
@@ -99,6 +102,17 @@ __device__ __forceinline__ void cplx_put(__bf16 *re, __bf16 *im, s2v v)
     *reinterpret_cast<short *>(im) = v[1];
 }
 
+// Operand fragment from four scalars of storage type T at four addresses (bits unchanged).
+__device__ __forceinline__ f4v op_gather4(const float *p0, const float *p1, const float *p2, const float *p3)
+{
+    return f4v{*p0, *p1, *p2, *p3};
+}
+__device__ __forceinline__ s4v op_gather4(const __bf16 *p0, const __bf16 *p1, const __bf16 *p2, const __bf16 *p3)
+{
+    return s4v{*reinterpret_cast<const short *>(p0), *reinterpret_cast<const short *>(p1),
+               *reinterpret_cast<const short *>(p2), *reinterpret_cast<const short *>(p3)};
+}
+
 // Operand fragment from four scalars of storage type T, `stride` elements apart (bits unchanged).
 __device__ __forceinline__ f4v op_gather(const float *p, int stride)
 {
@@ -144,6 +158,10 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     T *uim = ure + a.uim_off;
     T *vl = reinterpret_cast<T *>(smem + a.off_v);
     T *xt = reinterpret_cast<T *>(smem + a.off_x);
+    // transposed source: element (t, k) sits in row t at column xsw(t, k): bits 2-3 of k (the
+    // 4-value chunk within each 16-column block) are XORed with bits of t, so that the 16 rows
+    // one fragment read touches fall in distinct banks
+    auto xsw = [](int t, int k) { return k ^ (((t >> (NTQ == 2 ? 3 : 2)) & 3) << 2); };
 
     // ---- one-time set-up: zero U (padding kz >= Kz stays zero) and the transposed source
     // (rows t >= Nt, channels ci >= Csrc and the over-read pad stay zero)
@@ -226,9 +244,11 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
         const int pr = e % npair, cq = e / npair, zl = pr / nt4, t4 = pr - zl * nt4;
         Op r[4];
         op_transpose4(v, r);
-        T *d = xt + (size_t)(4 * t4) * ldT + zl * Csp + 4 * cq;
 #pragma unroll
-        for (int jj = 0; jj < 4; jj++) *reinterpret_cast<Op *>(d + (size_t)jj * ldT) = r[jj];
+        for (int jj = 0; jj < 4; jj++) {
+            const int t = 4 * t4 + jj;
+            *reinterpret_cast<Op *>(xt + (size_t)t * ldT + xsw(t, zl * Csp + 4 * cq)) = r[jj];
+        }
     };
     const int ngroups = ZC / ZG;
     const int QH = a.QZ / 2;
@@ -353,14 +373,15 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                 for (int q = 0; q < NTT; q++)
                     bv[q] = *reinterpret_cast<const Op *>(vl + (size_t)vrow * ldv + 16 * q + 4 * (g ^ vswz(vrow)));
                 // A[t][k = 16 (qlo + s) + 4 g + jj] for row c of t tile mt: t = 4 NTQ (c / 4) + 4 mt + c % 4
-                const T *xa = xt + (size_t)(4 * NTQ * (c >> 2) + (c & 3)) * ldT + gi * ZG * Csp + 16 * qlo + 4 * g;
+                const int xrow = 4 * NTQ * (c >> 2) + (c & 3), xk = gi * ZG * Csp + 16 * qlo + 4 * g;
                 Op av[has_src_c<EPI>() ? SPAN : 1][NTQ];
                 if (PW) {
 #pragma unroll
                     for (int s = 0; s < SPAN; s++)
 #pragma unroll
                         for (int mt = 0; mt < NTQ; mt++)
-                            av[s][mt] = has_src ? *reinterpret_cast<const Op *>(xa + (size_t)4 * mt * ldT + 16 * s)
+                            av[s][mt] = has_src ? *reinterpret_cast<const Op *>(
+                                                      xt + (size_t)(xrow + 4 * mt) * ldT + xsw(xrow + 4 * mt, xk + 16 * s))
                                                 : op_zero<T>();
                 }
                 f4v acc[NTQ];
@@ -413,13 +434,16 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                 }
                 if (EPI == ZEPI_BWD) {
                     // C[(z', i) = 16 (qlo + s) + 4 g + r][n] += sum_t x[z'][i][t] gz[n][t]; K chunk = t tile mt
-                    const T *xg = xt + (size_t)(4 * NTQ * g) * ldT + gi * ZG * Csp + 16 * qlo + c;
+                    const int grow = 4 * NTQ * g, gk = gi * ZG * Csp + 16 * qlo + c;
 #pragma unroll
                     for (int mt = 0; mt < NTQ; mt++) {
                         const Op bg = to_op<T>(acc[mt]);
 #pragma unroll
                         for (int s = 0; s < NGW; s++) {
-                            const Op ax = op_gather(xg + (size_t)4 * mt * ldT + 16 * s, ldT);
+                            const int r0 = grow + 4 * mt, k = gk + 16 * s;
+                            const T *xg = xt + (size_t)r0 * ldT;
+                            const Op ax = op_gather4(xg + xsw(r0, k), xg + ldT + xsw(r0 + 1, k),
+                                                     xg + 2 * ldT + xsw(r0 + 2, k), xg + 3 * ldT + xsw(r0 + 3, k));
                             gwacc[s] = mma16(ax, bg, gwacc[s]);
                         }
                     }
@@ -475,8 +499,10 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
 #define FNO_ZT_KERNEL(NAME, EPI)                                                                                  \
     template <typename T, int NTT, int NTQ, int SPAN, bool SPLIT, int MAXW>                                        \
     __global__ void __launch_bounds__(64 * MAXW)                                                                   \
-        __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? FNO_ZT_WAVES_F32                                      \
-                                                              : (EPI == ZEPI_BWD ? FNO_ZT_WAVES_BWD : FNO_ZT_WAVES_BF16)))) \
+        __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4          ? FNO_ZT_WAVES_F32                           \
+                                           : EPI == ZEPI_BWD   ? FNO_ZT_WAVES_BWD                                   \
+                                           : EPI == ZEPI_BLOCK ? FNO_ZT_WAVES_BLOCK                                 \
+                                                               : FNO_ZT_WAVES_ADJ)))                                \
         NAME(const typename CplxOf<T>::type *__restrict__ u, T *__restrict__ out, const T *__restrict__ src,       \
              const T *__restrict__ gy,                                                                             \
              const float *__restrict__ wpw, const float *__restrict__ bpw, float *__restrict__ part,                \
@@ -565,7 +591,10 @@ static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, int target, Z
         const int qlo = ((16 * j) / Cs * a.Csp) / 16;
         reach = std::max(reach, (16 - a.ZG) * a.Csp + 16 * (qlo + a.SPAN));
     }
-    a.ldT = (reach + 3) / 4 * 4;
+    // rows cover whole 16-column blocks (the chunk swizzle stays inside a block), and the row
+    // stride is 8 words mod 32 (see the kernel's xsw)
+    a.ldT = (reach + 15) / 16 * 16;
+    while ((a.ldT * elem / 4) % 32 != 8) a.ldT += 4;
     const int ntt = d.K[3] <= 8 ? 1 : 2;
     // imaginary plane at a word offset = 16 (mod 32) from the real one
     a.uim_off = Cs * a.Kt * a.Kzp;
