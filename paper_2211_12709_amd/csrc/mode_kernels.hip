@@ -104,6 +104,90 @@ __global__ void k_mix_bwd_w(const float2 *__restrict__ xh, const float2 *__restr
     }
 }
 
+// Tiled mix: a workgroup owns 64 consecutive retained modes; the batch's X^ (or gY^) of all
+// channels at those modes is staged in LDS once, and the 4 groups of 64 lanes split the output
+// channels, so every W element is read once (and, in the backward, gW written once) in
+// coalesced 512-byte rows while X^ / gY^ are read once.
+constexpr int kMixK = 64;
+
+// Y^[b][o][k] = sum_i X^[b][i][k] W[i][o][k]
+__global__ void __launch_bounds__(256) k_mix_fwd_t(const float2 *__restrict__ xh, const float2 *__restrict__ w,
+                                                   float2 *__restrict__ yh, int B, int Ci, int Co, long long M)
+{
+    extern __shared__ float2 xs[];  // [b][i][kMixK]
+    const int tk = threadIdx.x % kMixK, to = threadIdx.x / kMixK;
+    const long long k0 = (long long)blockIdx.x * kMixK, k = k0 + tk;
+    for (int e = threadIdx.x; e < B * Ci * kMixK; e += 256) {
+        const int bi = e / kMixK, kk = e % kMixK;
+        xs[e] = k0 + kk < M ? xh[(long long)bi * M + k0 + kk] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    if (k >= M) return;
+    for (int o = to; o < Co; o += 4)
+        for (int b = 0; b < B; b++) {
+            float re = 0.f, im = 0.f;
+            for (int i = 0; i < Ci; i++) {
+                const float2 a = xs[(b * Ci + i) * kMixK + tk];
+                const float2 q = w[((long long)i * Co + o) * M + k];
+                re += a.x * q.x - a.y * q.y;
+                im += a.x * q.y + a.y * q.x;
+            }
+            yh[((long long)b * Co + o) * M + k] = make_float2(re, im);
+        }
+}
+
+// gX^[b][i][k] = sum_o gY^[b][o][k] conj(W[i][o][k]) and gW[i][o][k] (+)= sum_b conj(X^[b][i][k]) gY^[b][o][k],
+// one pass over W and gW (either output may be null; with gw null, xh may be null).
+__global__ void __launch_bounds__(256) k_mix_bwd_t(const float2 *__restrict__ xh, const float2 *__restrict__ w,
+                                                   const float2 *__restrict__ gyh, float2 *__restrict__ gxh,
+                                                   float2 *__restrict__ gw, int B, int Ci, int Co, long long M,
+                                                   int accumulate)
+{
+    extern __shared__ float2 sh[];  // gs [b][o][kMixK], then xs [b][i][kMixK]
+    float2 *gs = sh, *xs = sh + (size_t)B * Co * kMixK;
+    const int tk = threadIdx.x % kMixK, ti = threadIdx.x / kMixK;
+    const long long k0 = (long long)blockIdx.x * kMixK, k = k0 + tk;
+    for (int e = threadIdx.x; e < B * Co * kMixK; e += 256) {
+        const int bo = e / kMixK, kk = e % kMixK;
+        gs[e] = k0 + kk < M ? gyh[(long long)bo * M + k0 + kk] : make_float2(0.f, 0.f);
+    }
+    if (gw)
+        for (int e = threadIdx.x; e < B * Ci * kMixK; e += 256) {
+            const int bi = e / kMixK, kk = e % kMixK;
+            xs[e] = k0 + kk < M ? xh[(long long)bi * M + k0 + kk] : make_float2(0.f, 0.f);
+        }
+    __syncthreads();
+    if (k >= M) return;
+    for (int i = ti; i < Ci; i += 4) {
+        for (int b = 0; b < (gxh ? B : 0); b++) {
+            float re = 0.f, im = 0.f;
+            for (int o = 0; o < Co; o++) {
+                const float2 g = gs[(b * Co + o) * kMixK + tk];
+                const float2 q = w[((long long)i * Co + o) * M + k];
+                re += g.x * q.x + g.y * q.y;
+                im += g.y * q.x - g.x * q.y;
+            }
+            gxh[((long long)b * Ci + i) * M + k] = make_float2(re, im);
+        }
+        if (gw)
+            for (int o = 0; o < Co; o++) {
+                float re = 0.f, im = 0.f;
+                for (int b = 0; b < B; b++) {
+                    const float2 a = xs[(b * Ci + i) * kMixK + tk], g = gs[(b * Co + o) * kMixK + tk];
+                    re += a.x * g.x + a.y * g.y;
+                    im += a.x * g.y - a.y * g.x;
+                }
+                const long long wi = ((long long)i * Co + o) * M + k;
+                if (accumulate) {
+                    const float2 p0 = gw[wi];
+                    re += p0.x;
+                    im += p0.y;
+                }
+                gw[wi] = make_float2(re, im);
+            }
+    }
+}
+
 // Pointwise-weight gradient partials: for chunk c of the flat (b, n) range and
 // channel o, part[c][o][i] = sum gz[b][o][n] x[b][i][n] (i < Ci) and
 // part[c][o][Ci] = sum gz[b][o][n].  One workgroup per (chunk, o).
@@ -191,12 +275,24 @@ void launch_axis(const float2 *in, float2 *out, const float2 *tab, long long out
 
 void launch_mix_fwd(const float2 *xh, const float2 *w, float2 *yh, int B, int Ci, int Co, long long M, hipStream_t st)
 {
+    const size_t lds = sizeof(float2) * (size_t)B * Ci * kMixK;
+    if (lds <= 64 * 1024) {
+        hipLaunchKernelGGL(k_mix_fwd_t, dim3((unsigned)((M + kMixK - 1) / kMixK)), dim3(256), lds, st, xh, w, yh, B, Ci,
+                           Co, M);
+        return;
+    }
     hipLaunchKernelGGL(k_mix_fwd, dim3(grid_for((long long)B * Co * M, 256)), dim3(256), 0, st, xh, w, yh, B, Ci, Co, M);
 }
 
 void launch_mix_bwd(const float2 *xh, const float2 *w, const float2 *gyh, float2 *gxh, float2 *gw, int B, int Ci,
                     int Co, long long M, int accumulate, hipStream_t st)
 {
+    const size_t lds = sizeof(float2) * (size_t)B * (Co + (gw ? Ci : 0)) * kMixK;
+    if (lds <= 64 * 1024) {
+        hipLaunchKernelGGL(k_mix_bwd_t, dim3((unsigned)((M + kMixK - 1) / kMixK)), dim3(256), lds, st, xh, w, gyh, gxh,
+                           gw, B, Ci, Co, M, accumulate);
+        return;
+    }
     if (gxh)
         hipLaunchKernelGGL(k_mix_bwd_x, dim3(grid_for((long long)B * Ci * M, 256)), dim3(256), 0, st, gyh, w, gxh, B,
                            Ci, Co, M);
