@@ -22,6 +22,9 @@
 //            synthesis and the pointwise 1x1 land in one accumulator, four consecutive t per lane.
 //            Wave w always computes tile j = w mod NT (of groups w / NT, w / NT + R, ...), so its
 //            column map, pointwise-weight fragments and EPI_BWD accumulators stay in registers.
+//   bfloat16: phase 1 takes the chunk's z-basis fragments from registers (one round of loads per
+//            chunk instead of a dependent load per K step), and EPI_BWD / EPI_ADJ load each
+//            tile's epilogue operand one z chunk ahead (across planes at the last chunk).
 //   EPI_BWD  the gradient tile is then the B operand of
 //              C[(z', i)][(z, o)] += sum_t x[z'][i][t] gz[z][o][t];
 //            its z' = z entries, summed over z, are the pointwise-weight gradient.
@@ -37,13 +40,13 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3 };
 #define FNO_ZT_PREFETCH 0  // load the next z chunk's source during the current chunk's phase 2
 #endif
 #ifndef FNO_ZT_WAVES_BLOCK
-#define FNO_ZT_WAVES_BLOCK 6  // waves per SIMD the bfloat16 BLOCK kernel is compiled for
+#define FNO_ZT_WAVES_BLOCK 5  // waves per SIMD the bfloat16 BLOCK kernel is compiled for
 #endif
 #ifndef FNO_ZT_WAVES_ADJ
 #define FNO_ZT_WAVES_ADJ 5  // the same for the bfloat16 ADJ and PLAIN kernels
 #endif
 #ifndef FNO_ZT_WAVES_BWD
-#define FNO_ZT_WAVES_BWD 5  // the same for the bfloat16 BWD kernel
+#define FNO_ZT_WAVES_BWD 4  // the same for the bfloat16 BWD kernel
 #endif
 #ifndef FNO_ZT_WAVES_F32
 #define FNO_ZT_WAVES_F32 3  // the same for every float kernel
@@ -252,6 +255,9 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     };
     const int ngroups = ZC / ZG;
     const int QH = a.QZ / 2;
+    // bfloat16: the z-basis K chunks of a z chunk are held in registers when 2 Kzp / 16 <= QZM
+    constexpr int QZM = 4;
+    const bool tz_reg = sizeof(T) == 2 && a.QZ <= QZM;
     __syncthreads();
 
     const long long nplanes = (long long)a.B * nxy;
@@ -259,14 +265,50 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
         const long long bb = pl / nxy;
         return src + bb * Csrc * ncell + (pl - bb * nxy) * plane;
     };
+    // element offset of this lane's column (zr, co) at z = 0 and its first t = 4 NTQ g, in plane pl
+    auto col_of = [&](long long pl) {
+        const long long bb = pl / nxy;
+        return (bb * Cs + co) * ncell + (pl - bb * nxy) * plane + (long long)zr * Nt + 4 * NTQ * g;
+    };
+    // The epilogue operand (gy for EPI_BWD, the accumulated output for EPI_ADJ).  bfloat16 (AHEAD):
+    // group j of this wave has its operand loaded one z chunk ahead into ext[j] (the host keeps
+    // the groups per wave within JM); float: one tile ahead.
+    constexpr bool EXT = EPI == ZEPI_BWD || EPI == ZEPI_ADJ;
+    constexpr bool AHEAD = EXT && sizeof(T) == 2;
+    constexpr int JM = AHEAD ? 4 : 1;
+    Op ext[JM][NTQ];
+    auto load_ext = [&](long long ec, int z0, Op(&e)[NTQ]) {
+        const T *base = EPI == ZEPI_BWD ? gy : out;
+        const bool want = EPI == ZEPI_BWD || (EPI == ZEPI_ADJ && a.accumulate);
+        const bool zin = z0 < Nz && z0 + zr < Nz;
+        const long long ei = ec + (long long)z0 * Nt;
+#pragma unroll
+        for (int mt = 0; mt < NTQ; mt++) e[mt] = op_zero<T>();
+        bool whole = false;
+        if constexpr (NTQ == 2) {
+            whole = want && zin && 8 * g + 8 <= Nt;
+            if (whole) load8(base + ei, e[0], e[1]);
+        }
+        if (!whole) {
+#pragma unroll
+            for (int mt = 0; mt < NTQ; mt++)
+                if (want && zin && 4 * NTQ * g + 4 * mt < Nt) e[mt] = *reinterpret_cast<const Op *>(base + ei + 4 * mt);
+        }
+    };
+    if (AHEAD && (long long)blockIdx.x < nplanes) {
+        const long long ec0 = col_of(blockIdx.x);
+#pragma unroll
+        for (int j = 0; j < JM; j++)
+            if (tr + j * R < ngroups) load_ext(ec0, (tr + j * R) * ZG, ext[j]);
+    }
     if (sp_fast && (long long)blockIdx.x < nplanes) prefetch(plane_src(blockIdx.x), Nz);
     for (long long pl = blockIdx.x; pl < nplanes; pl += gridDim.x) {
         const int b = (int)(pl / nxy);
         const long long xy = pl % nxy;
         const T *srcp = src + (long long)b * Csrc * ncell + xy * plane;
-        const T *srcn = pl + gridDim.x < nplanes ? plane_src(pl + gridDim.x) : srcp;  // next plane
-        // element offset of this lane's column (zr, co) at z = 0 and its first t = 4 NTQ g
-        const long long ecol = ((long long)b * Cs + co) * ncell + xy * plane + (long long)zr * Nt + 4 * NTQ * g;
+        const bool has_next = pl + gridDim.x < nplanes;
+        const T *srcn = has_next ? plane_src(pl + gridDim.x) : srcp;  // next plane
+        const long long ecol = col_of(pl), ecol_n = has_next ? col_of(pl + gridDim.x) : ecol;
         __syncthreads();  // previous plane's readers of U are done
         // ---- phase 0: U of every channel, to [c][kz / 4][kt][kz % 4]
         if (u_ok)
@@ -282,28 +324,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
             }
         for (int zc0 = 0; zc0 < Nz; zc0 += ZC) {
             __syncthreads();  // U staged / previous chunk's V and source consumed
-            // early loads of the first tile's epilogue operand (gy, or the accumulated output)
-            Op ext[NTQ];
-            auto load_ext = [&](int z0, Op(&e)[NTQ]) {
-                const T *base = EPI == ZEPI_BWD ? gy : out;
-                const bool want = EPI == ZEPI_BWD || (EPI == ZEPI_ADJ && a.accumulate);
-                const bool zin = z0 < Nz && z0 + zr < Nz;
-                const long long ei = ecol + (long long)z0 * Nt;
-#pragma unroll
-                for (int mt = 0; mt < NTQ; mt++) e[mt] = op_zero<T>();
-                bool whole = false;
-                if constexpr (NTQ == 2) {
-                    whole = want && zin && 8 * g + 8 <= Nt;
-                    if (whole) load8(base + ei, e[0], e[1]);
-                }
-                if (!whole) {
-#pragma unroll
-                    for (int mt = 0; mt < NTQ; mt++)
-                        if (want && zin && 4 * NTQ * g + 4 * mt < Nt)
-                            e[mt] = *reinterpret_cast<const Op *>(base + ei + 4 * mt);
-                }
-            };
-            if (EPI == ZEPI_BWD || EPI == ZEPI_ADJ) load_ext(zc0 + tr * ZG, ext);
+            if (EXT && !AHEAD) load_ext(ecol, zc0 + tr * ZG, ext[0]);
             // source chunk -> LDS transposed [t][(zl, ci)]
             if (sp_fast) {
 #pragma unroll
@@ -324,7 +345,23 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                 }
             }
             // ---- phase 1: V^T tiles (channel cs, (re/im, kt) tile mt) of this z tile into LDS
+            // z-basis fragments of this chunk (cos rows, then sin rows), loaded once per wave for
+            // all of its items
             const int zg = zc0 / 16;
+            Op tzc[QZM / 2], tzs[QZM / 2], tzcl[QZM / 2], tzsl[QZM / 2];
+            if (tz_reg) {
+#pragma unroll
+                for (int q = 0; q < QZM / 2; q++)
+                    if (q < QH) {
+                        const int ti = (zg * a.QZ + q) * 64 + lane, si = ti + QH * 64;
+                        tzc[q] = tabZ[ti];
+                        tzs[q] = tabZ[si];
+                        if (SPLIT) {
+                            tzcl[q] = tabZ_lo[ti];
+                            tzsl[q] = tabZ_lo[si];
+                        }
+                    }
+            }
             for (int item = w; item < Cs * NTT; item += NW) {
                 const int cs = NTT == 1 ? item : item >> 1, mt = NTT == 1 ? 0 : item & 1;
                 const int ri = NTT == 1 ? (c >> 3) : mt;
@@ -336,18 +373,32 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                 const T *p_sin = (ri == 0 ? uim : ure) + roff;  // multiplies sin (negated for ri = 0)
                 const int qstep = 16 * Kt;
                 f4v acc = f4_zero();
-                for (int q = 0; q < QH; q++) {
-                    const Op av = krow ? *reinterpret_cast<const Op *>(p_cos + qstep * q) : op_zero<T>();
-                    const int ti = (zg * a.QZ + q) * 64 + lane;
-                    acc = mma16(av, tabZ[ti], acc);
-                    if (SPLIT) acc = mma16(av, tabZ_lo[ti], acc);
-                }
-                for (int q = 0; q < QH; q++) {
-                    const Op av =
-                        krow ? op_sign(*reinterpret_cast<const Op *>(p_sin + qstep * q), ri == 0) : op_zero<T>();
-                    const int ti = (zg * a.QZ + QH + q) * 64 + lane;
-                    acc = mma16(av, tabZ[ti], acc);
-                    if (SPLIT) acc = mma16(av, tabZ_lo[ti], acc);
+                if (tz_reg) {
+#pragma unroll
+                    for (int q = 0; q < QZM / 2; q++)
+                        if (q < QH) {
+                            const Op ac = krow ? *reinterpret_cast<const Op *>(p_cos + qstep * q) : op_zero<T>();
+                            const Op as = krow ? op_sign(*reinterpret_cast<const Op *>(p_sin + qstep * q), ri == 0)
+                                               : op_zero<T>();
+                            acc = mma16(ac, tzc[q], acc);
+                            if (SPLIT) acc = mma16(ac, tzcl[q], acc);
+                            acc = mma16(as, tzs[q], acc);
+                            if (SPLIT) acc = mma16(as, tzsl[q], acc);
+                        }
+                } else {
+                    for (int q = 0; q < QH; q++) {
+                        const Op av = krow ? *reinterpret_cast<const Op *>(p_cos + qstep * q) : op_zero<T>();
+                        const int ti = (zg * a.QZ + q) * 64 + lane;
+                        acc = mma16(av, tabZ[ti], acc);
+                        if (SPLIT) acc = mma16(av, tabZ_lo[ti], acc);
+                    }
+                    for (int q = 0; q < QH; q++) {
+                        const Op av =
+                            krow ? op_sign(*reinterpret_cast<const Op *>(p_sin + qstep * q), ri == 0) : op_zero<T>();
+                        const int ti = (zg * a.QZ + QH + q) * 64 + lane;
+                        acc = mma16(av, tabZ[ti], acc);
+                        if (SPLIT) acc = mma16(av, tabZ_lo[ti], acc);
+                    }
                 }
                 // acc[r] = V^T[(ri, kt) = 16 mt + 4 g + r][z = zc0 + c]
                 float v[4] = {acc[0], acc[1], acc[2], acc[3]};
@@ -360,12 +411,8 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                 if (zc0 + ZC < Nz) prefetch(srcp + (long long)(zc0 + ZC) * Nt, Nz - zc0 - ZC);
                 else prefetch(srcn, pl + gridDim.x < nplanes ? Nz : 0);
             }
-            // ---- phase 2: this wave's tile of groups tr, tr + R, ...
-            for (int gi = tr; gi < ngroups; gi += R) {
-                const int z0 = zc0 + gi * ZG;
-                if (z0 >= Nz) break;
-                Op ext_next[NTQ];
-                if (EPI == ZEPI_BWD || EPI == ZEPI_ADJ) load_ext(gi + R < ngroups ? z0 + R * ZG : Nz, ext_next);
+            // ---- phase 2: this wave's tile of group gi (first z0), epilogue operand ext_c
+            auto tile = [&](int gi, int z0, const Op(&ext_c)[NTQ]) {
                 // operands: V columns (B of the synthesis) and the transposed source (A of the 1x1)
                 const int vrow = gi * ZG * Cs + 16 * tj + c;
                 Op bv[NTT];
@@ -412,13 +459,13 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                     } else if (EPI == ZEPI_BWD) {
 #pragma unroll
                         for (int r = 0; r < 4; r++) {
-                            v[mt][r] = ok ? op_get(ext[mt], r) * gelu_grad_fast(v[mt][r] + bj) : 0.f;
+                            v[mt][r] = ok ? op_get(ext_c[mt], r) * gelu_grad_fast(v[mt][r] + bj) : 0.f;
                             gbacc += v[mt][r];
                         }
                         acc[mt] = f4v{v[mt][0], v[mt][1], v[mt][2], v[mt][3]};  // gradient tile, B of the product below
                     } else if (EPI == ZEPI_ADJ) {
 #pragma unroll
-                        for (int r = 0; r < 4; r++) v[mt][r] += op_get(ext[mt], r);
+                        for (int r = 0; r < 4; r++) v[mt][r] += op_get(ext_c[mt], r);
                     }
                 }
                 T *op = out + ecol + (long long)z0 * Nt;
@@ -448,9 +495,33 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                         }
                     }
                 }
-                if (EPI == ZEPI_BWD || EPI == ZEPI_ADJ) {
+            };
+            if constexpr (AHEAD) {
 #pragma unroll
-                    for (int mt = 0; mt < NTQ; mt++) ext[mt] = ext_next[mt];
+                for (int j = 0; j < JM; j++) {
+                    // gi is the same in every chunk: hide that, or the LDS addresses of all JM
+                    // tiles are hoisted out of the chunk loop and held in registers throughout
+                    int gi = tr + j * R;
+                    asm volatile("" : "+v"(gi));
+                    if (gi < ngroups) {
+                        const int z0 = zc0 + gi * ZG;
+                        if (z0 < Nz) tile(gi, z0, ext[j]);
+                        // the same group of the next chunk, else of the next plane's first chunk
+                        if (zc0 + ZC < Nz) load_ext(ecol, z0 + ZC, ext[j]);
+                        else load_ext(ecol_n, has_next ? gi * ZG : Nz, ext[j]);
+                    }
+                }
+            } else {
+                for (int gi = tr; gi < ngroups; gi += R) {
+                    const int z0 = zc0 + gi * ZG;
+                    if (z0 >= Nz) break;
+                    Op en[NTQ];
+                    if (EXT) load_ext(ecol, gi + R < ngroups ? z0 + R * ZG : Nz, en);
+                    tile(gi, z0, ext[0]);
+                    if (EXT) {
+#pragma unroll
+                        for (int mt = 0; mt < NTQ; mt++) ext[0][mt] = en[mt];
+                    }
                 }
             }
         }
@@ -548,13 +619,17 @@ static int gcd_int(int a, int b)
 static size_t al16(size_t v) { return (v + 15) / 16 * 16; }
 
 // Geometry and LDS carve-up of one launch; returns the LDS bytes (0: shape not supported).
+static bool zt_ext(int epi) { return epi == ZEPI_BWD || epi == ZEPI_ADJ; }
+
 static int zt_target_waves(int epi, int elem)
 {
     if (elem == 4) return FNO_ZT_TARGET_F32;
     return epi == ZEPI_BLOCK ? FNO_ZT_TARGET_BLOCK : epi == ZEPI_BWD ? FNO_ZT_TARGET_BWD : FNO_ZT_TARGET_ADJ;
 }
 
-static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, int target, ZtArgs &a)
+// ext: the epilogue reads an operand per output tile (EPI_BWD, EPI_ADJ); for bfloat16 the kernel
+// keeps it one z chunk ahead for at most 4 groups per wave.
+static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, int target, bool ext, ZtArgs &a)
 {
     a = ZtArgs{};
     a.B = d.B;
@@ -575,7 +650,10 @@ static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, int target, Z
     if (a.NT > kZtMaxWaves) return 0;
     // waves per tile index: about `target` waves in all (at most 16), never more than there are groups
     a.R = std::max(1, std::min(16 / a.ZG, (target + a.NT - 1) / a.NT));
+    const bool ahead = ext && elem == 2;
+    if (ahead) a.R = std::max(a.R, (16 / a.ZG + 3) / 4);
     while (a.NT * a.R > kZtMaxWaves) a.R--;
+    if (ahead && (16 / a.ZG + a.R - 1) / a.R > 4) return 0;
     int span = 1;
     for (int j = 0; j < a.NT && Csrc > 0; j++) {
         const int zlo = (16 * j) / Cs, zhi = (16 * j + 15) / Cs;
@@ -612,7 +690,7 @@ static bool zt_pair_ok(const Dims &d, int Cs, int Csrc, int elem)
 {
     for (int epi = ZEPI_PLAIN; epi <= ZEPI_ADJ; epi++) {
         ZtArgs a;
-        const size_t lds = zt_layout(d, Cs, Csrc, elem, zt_target_waves(epi, elem), a);
+        const size_t lds = zt_layout(d, Cs, Csrc, elem, zt_target_waves(epi, elem), zt_ext(epi), a);
         if (lds == 0 || lds > 160 * 1024) return false;
     }
     return true;
@@ -639,7 +717,7 @@ static hipError_t launch_zt_t(const Dims &d, int Cs, int Csrc, int accumulate, c
     typedef typename OpOf<T>::type Op;
     constexpr bool split = sizeof(T) == 2;
     ZtArgs a;
-    const size_t lds = zt_layout(d, Cs, Csrc, sizeof(T), zt_target_waves(EPI, sizeof(T)), a);
+    const size_t lds = zt_layout(d, Cs, Csrc, sizeof(T), zt_target_waves(EPI, sizeof(T)), zt_ext(EPI), a);
     if (lds == 0) return hipErrorInvalidValue;
     a.accumulate = accumulate;
     const int nth = 64 * a.NT * a.R;
@@ -674,7 +752,8 @@ hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const void *u, T 
                      int *rows_used)
 {
     ZtArgs a;
-    if (zt_layout(d, Cs, Csrc, sizeof(T), zt_target_waves(epi, sizeof(T)), a) == 0) return hipErrorInvalidValue;
+    if (zt_layout(d, Cs, Csrc, sizeof(T), zt_target_waves(epi, sizeof(T)), zt_ext(epi), a) == 0)
+        return hipErrorInvalidValue;
     const bool w8 = a.NT * a.R <= 8;
     const int sel = (d.K[3] <= 8 ? 0 : 6) + (a.NTQ == 1 ? 0 : 3) + std::min(2, std::max(0, a.SPAN - 2));
 #define FNO_ZT_W(E, NTT_, NTQ_, SPAN_)                                                                              \
