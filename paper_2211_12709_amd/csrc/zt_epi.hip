@@ -39,6 +39,9 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3 };
 #ifndef FNO_ZT_PREFETCH
 #define FNO_ZT_PREFETCH 0  // load the next z chunk's source during the current chunk's phase 2
 #endif
+#ifndef FNO_ZT_UBATCH
+#define FNO_ZT_UBATCH 2  // bfloat16 U staging items loaded together per thread (float: half)
+#endif
 #ifndef FNO_ZT_WAVES_BLOCK
 #define FNO_ZT_WAVES_BLOCK 5  // waves per SIMD the bfloat16 BLOCK kernel is compiled for
 #endif
@@ -103,6 +106,44 @@ __device__ __forceinline__ void cplx_put(__bf16 *re, __bf16 *im, s2v v)
 {
     *reinterpret_cast<short *>(re) = v[0];
     *reinterpret_cast<short *>(im) = v[1];
+}
+
+// Four consecutive spectrum elements (re, im pairs) in one register group, and their scatter into
+// the real and imaginary U planes at element stride 4 (consecutive kt of one kz).
+struct F8 {
+    f4v a, b;
+};
+template <typename T> struct U4Of;
+template <> struct U4Of<float> { typedef F8 type; };
+template <> struct U4Of<__bf16> { typedef s8v type; };
+__device__ __forceinline__ void u4_load(const float2 *p, F8 &v)
+{
+    v.a = *reinterpret_cast<const f4v *>(p);
+    v.b = *reinterpret_cast<const f4v *>(p + 2);
+}
+__device__ __forceinline__ void u4_load(const s2v *p, s8v &v) { v = *reinterpret_cast<const s8v *>(p); }
+__device__ __forceinline__ void u4_put(float *re, float *im, const F8 &v)
+{
+    re[0] = v.a[0];
+    im[0] = v.a[1];
+    re[4] = v.a[2];
+    im[4] = v.a[3];
+    re[8] = v.b[0];
+    im[8] = v.b[1];
+    re[12] = v.b[2];
+    im[12] = v.b[3];
+}
+__device__ __forceinline__ void u4_put(__bf16 *re_, __bf16 *im_, const s8v &v)
+{
+    short *re = reinterpret_cast<short *>(re_), *im = reinterpret_cast<short *>(im_);
+    re[0] = v[0];
+    im[0] = v[1];
+    re[4] = v[2];
+    im[4] = v[3];
+    re[8] = v[4];
+    im[8] = v[5];
+    re[12] = v[6];
+    im[12] = v[7];
 }
 
 // Operand fragment from four scalars of storage type T at four addresses (bits unchanged).
@@ -219,6 +260,11 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     const int u_r0 = u_one ? (int)threadIdx.x % KK : (int)threadIdx.x;
     const int u_c0 = u_one ? (int)threadIdx.x / KK : 0;
     const bool u_ok = u_one ? (int)threadIdx.x < u_cstep * KK : true;
+    // vector staging when Kt % 4 == 0: 16-byte (bfloat16) or 32-byte (float) items (not in the
+    // bfloat16 EPI_BWD / EPI_ADJ kernels, whose register budget it overruns)
+    constexpr bool U_VEC = !(sizeof(T) == 2 && (EPI == ZEPI_BWD || EPI == ZEPI_ADJ));
+    const bool u_vec = U_VEC && Kt % 4 == 0;
+    const int KK4 = KK / 4, nu4 = Cs * KK4;
     // source staging: item (pair (zl, t4), channel quad cq) loads 4 consecutive t of channels
     // 4 cq .. 4 cq + 3, transposes them in registers and writes 4 rows t of 4 channels to LDS.
     // Fast path (at most SQ items per thread): the items are loaded one chunk ahead, during the
@@ -311,7 +357,31 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
         const long long ecol = col_of(pl), ecol_n = has_next ? col_of(pl + gridDim.x) : ecol;
         __syncthreads();  // previous plane's readers of U are done
         // ---- phase 0: U of every channel, to [c][kz / 4][kt][kz % 4]
-        if (u_ok)
+        if (u_vec) {
+            // items (channel, 4 consecutive kt of one kz); a batch's loads all precede its writes
+            constexpr int UB = sizeof(T) == 2 ? FNO_ZT_UBATCH : (FNO_ZT_UBATCH + 1) / 2;
+            const typename CplxOf<T>::type *ub = u + ((long long)b * Cs * nxy + xy) * KK;
+            for (int i0 = threadIdx.x; i0 < nu4; i0 += UB * NTH) {
+                typename U4Of<T>::type v[UB];
+#pragma unroll
+                for (int k = 0; k < UB; k++) {
+                    const int it = i0 + k * NTH;
+                    if (it < nu4) {
+                        const int cs = it / KK4, r = 4 * (it - cs * KK4);
+                        u4_load(ub + (long long)cs * nxy * KK + r, v[k]);
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < UB; k++) {
+                    const int it = i0 + k * NTH;
+                    if (it < nu4) {
+                        const int cs = it / KK4, r = 4 * (it - cs * KK4), kz = r / Kt, kt = r - kz * Kt;
+                        const size_t ul = (size_t)cs * Kt * Kzp + ((size_t)(kz >> 2) * Kt + kt) * 4 + (kz & 3);
+                        u4_put(ure + ul, uim + ul, v[k]);
+                    }
+                }
+            }
+        } else if (u_ok)
             for (int r = u_r0; r < KK; r += (u_one ? KK : NTH)) {
                 const int kz = r / Kt, kt = r - kz * Kt;
                 const typename CplxOf<T>::type *up = u + ((long long)b * Cs * nxy + xy) * KK + r;
