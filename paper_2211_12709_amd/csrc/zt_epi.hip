@@ -36,8 +36,11 @@ namespace fno {
 enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3 };
 
 // Tuning knobs of the launch (defaults are the measured best on MI355X).
-#ifndef FNO_ZT_PREFETCH
-#define FNO_ZT_PREFETCH 0  // load the next z chunk's source during the current chunk's phase 2
+#ifndef FNO_ZT_SBATCH
+#define FNO_ZT_SBATCH 2  // source staging items loaded together per thread
+#endif
+#ifndef FNO_ZT_SBATCH_EXT
+#define FNO_ZT_SBATCH_EXT 1  // the same for the bfloat16 ADJ kernel
 #endif
 #ifndef FNO_ZT_UBATCH
 #define FNO_ZT_UBATCH 2  // bfloat16 U staging items loaded together per thread (float: half)
@@ -265,32 +268,17 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     constexpr bool U_VEC = !(sizeof(T) == 2 && (EPI == ZEPI_BWD || EPI == ZEPI_ADJ));
     const bool u_vec = U_VEC && Kt % 4 == 0;
     const int KK4 = KK / 4, nu4 = Cs * KK4;
-    // source staging: item (pair (zl, t4), channel quad cq) loads 4 consecutive t of channels
+    // source staging: item (channel quad cq, z zl, t quad t4) loads 4 consecutive t of channels
     // 4 cq .. 4 cq + 3, transposes them in registers and writes 4 rows t of 4 channels to LDS.
-    // Fast path (at most SQ items per thread): the items are loaded one chunk ahead, during the
-    // previous chunk's phase 2, and written at the top of the chunk.
-    constexpr int SQ = 1;
-    const int nt4 = Nt / 4, npair = ZC * nt4, nquad = (Csrc + 3) / 4, nitem = npair * nquad;
-    const bool sp_fast = FNO_ZT_PREFETCH && has_src && nitem <= SQ * NTH;
-    Op pre[SQ][4];
-    // chunk whose channel-0 element (zl = 0, t = 0) is `cb` into pre; `zmax` = z values left in it
-    auto prefetch = [&](const T *cb, int zmax) {
-#pragma unroll
-        for (int m = 0; m < SQ; m++) {
-            const int e = threadIdx.x + m * NTH, pr = e % npair, cq = e / npair;
-            const int zl = pr / nt4, t4 = pr - zl * nt4;
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                const int ci = 4 * cq + k;
-                pre[m][k] = (e < nitem && zl < zmax && ci < Csrc)
-                                ? *reinterpret_cast<const Op *>(cb + (long long)zl * Nt + 4 * t4 + (long long)ci * ncell)
-                                : op_zero<T>();
-            }
-        }
-    };
-    // write item e's 4 x 4 block from v to LDS
-    auto put_item = [&](int e, const Op (&v)[4]) {
-        const int pr = e % npair, cq = e / npair, zl = pr / nt4, t4 = pr - zl * nt4;
+    // Items run over 4 NTQ t quads (a power of two; quads at or past Nt idle), so the item index
+    // splits by shifts; SB items per thread have their loads issued before their writes.
+    constexpr int LT4 = NTQ == 2 ? 3 : 2;
+    // (The bfloat16 EPI_BWD kernel measures faster with one item at a time over the Nt / 4 quads.)
+    constexpr bool SRC_SEQ = sizeof(T) == 2 && EPI == ZEPI_BWD;
+    constexpr int SB = (sizeof(T) == 2 && EPI == ZEPI_ADJ) ? FNO_ZT_SBATCH_EXT : FNO_ZT_SBATCH;
+    const int nitem = ((Csrc + 3) / 4) << (LT4 + 4);
+    const int nt4 = Nt / 4, npair = ZC * nt4, nitem_seq = npair * ((Csrc + 3) / 4);
+    auto put_item = [&](int cq, int zl, int t4, const Op (&v)[4]) {
         Op r[4];
         op_transpose4(v, r);
 #pragma unroll
@@ -307,10 +295,6 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     __syncthreads();
 
     const long long nplanes = (long long)a.B * nxy;
-    auto plane_src = [&](long long pl) {
-        const long long bb = pl / nxy;
-        return src + bb * Csrc * ncell + (pl - bb * nxy) * plane;
-    };
     // element offset of this lane's column (zr, co) at z = 0 and its first t = 4 NTQ g, in plane pl
     auto col_of = [&](long long pl) {
         const long long bb = pl / nxy;
@@ -347,13 +331,11 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
         for (int j = 0; j < JM; j++)
             if (tr + j * R < ngroups) load_ext(ec0, (tr + j * R) * ZG, ext[j]);
     }
-    if (sp_fast && (long long)blockIdx.x < nplanes) prefetch(plane_src(blockIdx.x), Nz);
     for (long long pl = blockIdx.x; pl < nplanes; pl += gridDim.x) {
         const int b = (int)(pl / nxy);
         const long long xy = pl % nxy;
         const T *srcp = src + (long long)b * Csrc * ncell + xy * plane;
         const bool has_next = pl + gridDim.x < nplanes;
-        const T *srcn = has_next ? plane_src(pl + gridDim.x) : srcp;  // next plane
         const long long ecol = col_of(pl), ecol_n = has_next ? col_of(pl + gridDim.x) : ecol;
         __syncthreads();  // previous plane's readers of U are done
         // ---- phase 0: U of every channel, to [c][kz / 4][kt][kz % 4]
@@ -396,12 +378,8 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
             __syncthreads();  // U staged / previous chunk's V and source consumed
             if (EXT && !AHEAD) load_ext(ecol, zc0 + tr * ZG, ext[0]);
             // source chunk -> LDS transposed [t][(zl, ci)]
-            if (sp_fast) {
-#pragma unroll
-                for (int m = 0; m < SQ; m++)
-                    if ((int)threadIdx.x + m * NTH < nitem) put_item(threadIdx.x + m * NTH, pre[m]);
-            } else if (has_src) {
-                for (int e = threadIdx.x; e < nitem; e += NTH) {
+            if (SRC_SEQ && has_src) {
+                for (int e = threadIdx.x; e < nitem_seq; e += NTH) {
                     const int pr = e % npair, cq = e / npair, zl = pr / nt4, t4 = pr - zl * nt4;
                     const T *sp = srcp + (long long)(zc0 + zl) * Nt + 4 * t4;
                     Op v[4];
@@ -411,7 +389,28 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                         v[k] = (zc0 + zl < Nz && ci < Csrc) ? *reinterpret_cast<const Op *>(sp + (long long)ci * ncell)
                                                             : op_zero<T>();
                     }
-                    put_item(e, v);
+                    put_item(cq, zl, t4, v);
+                }
+            } else if (has_src) {
+                for (int e0 = threadIdx.x; e0 < nitem; e0 += SB * NTH) {
+                    Op v[SB][4];
+#pragma unroll
+                    for (int m = 0; m < SB; m++) {
+                        const int e = e0 + m * NTH, t4 = e & (4 * NTQ - 1), zl = (e >> LT4) & 15, cq = e >> (LT4 + 4);
+                        const T *sp = srcp + (long long)(zc0 + zl) * Nt + 4 * t4;
+                        const bool ok = e < nitem && 4 * t4 < Nt && zc0 + zl < Nz;
+#pragma unroll
+                        for (int k = 0; k < 4; k++) {
+                            const int ci = 4 * cq + k;
+                            v[m][k] = (ok && ci < Csrc) ? *reinterpret_cast<const Op *>(sp + (long long)ci * ncell)
+                                                        : op_zero<T>();
+                        }
+                    }
+#pragma unroll
+                    for (int m = 0; m < SB; m++) {
+                        const int e = e0 + m * NTH, t4 = e & (4 * NTQ - 1), zl = (e >> LT4) & 15, cq = e >> (LT4 + 4);
+                        if (e < nitem && 4 * t4 < Nt) put_item(cq, zl, t4, v[m]);
+                    }
                 }
             }
             // ---- phase 1: V^T tiles (channel cs, (re/im, kt) tile mt) of this z tile into LDS
@@ -476,11 +475,6 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                 store4(vl + (size_t)vr * ldv + 16 * mt + 4 * (g ^ vswz(vr)), v);
             }
             __syncthreads();
-            // the next chunk's source: this plane's next chunk, else the next plane's first
-            if (sp_fast) {
-                if (zc0 + ZC < Nz) prefetch(srcp + (long long)(zc0 + ZC) * Nt, Nz - zc0 - ZC);
-                else prefetch(srcn, pl + gridDim.x < nplanes ? Nz : 0);
-            }
             // ---- phase 2: this wave's tile of group gi (first z0), epilogue operand ext_c
             auto tile = [&](int gi, int z0, const Op(&ext_c)[NTQ]) {
                 // operands: V columns (B of the synthesis) and the transposed source (A of the 1x1)
