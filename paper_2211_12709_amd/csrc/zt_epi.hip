@@ -36,6 +36,12 @@ namespace fno {
 enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3 };
 
 // Tuning knobs of the launch (defaults are the measured best on MI355X).
+#ifndef FNO_ZT_AHEAD_BWD
+#define FNO_ZT_AHEAD_BWD 0  // bfloat16 BWD: epilogue operands one z chunk ahead (else one tile)
+#endif
+#ifndef FNO_ZT_TZREG_BWD
+#define FNO_ZT_TZREG_BWD 0  // bfloat16 BWD: z-basis fragments in registers
+#endif
 #ifndef FNO_ZT_SBATCH
 #define FNO_ZT_SBATCH 2  // source staging items loaded together per thread
 #endif
@@ -52,7 +58,7 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3 };
 #define FNO_ZT_WAVES_ADJ 5  // the same for the bfloat16 ADJ and PLAIN kernels
 #endif
 #ifndef FNO_ZT_WAVES_BWD
-#define FNO_ZT_WAVES_BWD 4  // the same for the bfloat16 BWD kernel
+#define FNO_ZT_WAVES_BWD 5  // the same for the bfloat16 BWD kernel
 #endif
 #ifndef FNO_ZT_WAVES_F32
 #define FNO_ZT_WAVES_F32 3  // the same for every float kernel
@@ -191,7 +197,8 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     constexpr int ZC = 16;  // z values per chunk
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int NTH = blockDim.x, NW = NTH >> 6;
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+    // the wave index is uniform: keep it (and the tile indices derived from it) in scalar registers
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), g = lane >> 4, c = lane & 15;
     const int Nz = a.Nz, Nt = a.Nt, Kt = a.Kt, Kzp = a.Kzp, Cs = a.Cs, Csrc = a.Csrc, Csp = a.Csp;
     const int ZG = a.ZG, NT = a.NT, R = a.R, ldT = a.ldT, KK = a.Kz * Kt;
     const bool has_src = PW && Csrc > 0;
@@ -291,7 +298,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     const int QH = a.QZ / 2;
     // bfloat16: the z-basis K chunks of a z chunk are held in registers when 2 Kzp / 16 <= QZM
     constexpr int QZM = 4;
-    const bool tz_reg = sizeof(T) == 2 && a.QZ <= QZM;
+    const bool tz_reg = sizeof(T) == 2 && (EPI != ZEPI_BWD || FNO_ZT_TZREG_BWD) && a.QZ <= QZM;
     __syncthreads();
 
     const long long nplanes = (long long)a.B * nxy;
@@ -304,7 +311,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     // group j of this wave has its operand loaded one z chunk ahead into ext[j] (the host keeps
     // the groups per wave within JM); float: one tile ahead.
     constexpr bool EXT = EPI == ZEPI_BWD || EPI == ZEPI_ADJ;
-    constexpr bool AHEAD = EXT && sizeof(T) == 2;
+    constexpr bool AHEAD = EXT && sizeof(T) == 2 && (EPI != ZEPI_BWD || FNO_ZT_AHEAD_BWD);
     constexpr int JM = AHEAD ? 4 : 1;
     Op ext[JM][NTQ];
     auto load_ext = [&](long long ec, int z0, Op(&e)[NTQ]) {
