@@ -35,7 +35,7 @@ __global__ void __launch_bounds__(256) k_axis_mfma(const float2 *__restrict__ in
     typedef typename OpOf<TC>::type Op;
     constexpr bool SPLIT = sizeof(TC) == 2;
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), g = lane >> 4, c = lane & 15;
     const long long nchunk = (a.cols + 63) / 64;
     const long long o = blockIdx.x / nchunk;
     const long long col0 = (blockIdx.x % nchunk) * 64;
@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(256) k_axis_syn(const float2 *__restrict__ in,
     constexpr bool SPLIT = sizeof(TC) == 2;
     const int CB = a.CB;
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), g = lane >> 4, c = lane & 15;
     const long long nchunk = (a.cols + CB - 1) / CB;
     const long long o = blockIdx.x / nchunk;
     const long long col0 = (blockIdx.x % nchunk) * CB;

@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(256) k_proj_bwd(const T *__restrict__ x, const
 {
     typedef typename OpOf<T>::type Op;
     extern __shared__ __attribute__((aligned(16))) char smem[];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, g = lane >> 4, c = lane & 15;
+    const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), g = lane >> 4, c = lane & 15;
     const int ldh = 16 * MH + 4;
     T *ghl = reinterpret_cast<T *>(smem) + (size_t)w * 2 * 16 * ldh;  // this wave: gH^T [16 p][ldh], Hd^T [16 p][ldh]
     T *hdl = ghl + 16 * ldh;
