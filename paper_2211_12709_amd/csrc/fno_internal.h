@@ -99,35 +99,39 @@ __device__ __forceinline__ float gelu_grad_f(float u)
 
 // GELU and its derivative from one evaluation of erf by Abramowitz & Stegun,
 // Handbook of Mathematical Functions, formula 7.1.26:
-//   erf(x) = 1 - (a1 s + a2 s^2 + a3 s^3 + a4 s^4 + a5 s^5) exp(-x^2),  s = 1/(1 + p x),  x >= 0,
-// with absolute error at most 1.5e-7.  exp(-x^2) at x = u/sqrt(2) is also the
-// Gaussian density term of GELU'(u) = Phi(u) + u phi(u), so both cost one
-// exponential and one reciprocal.
+//   1 - erf(w) = (a1 s + a2 s^2 + a3 s^3 + a4 s^4 + a5 s^5) exp(-w^2),  s = 1/(1 + p w),  w >= 0,
+// with absolute error at most 1.5e-7.  At w = |u|/sqrt(2), q = (1 - erf(w)) / 2 is the Gaussian
+// tail beyond |u|, so Phi(u) = 1 - q for u >= 0 and q for u < 0, and
+//   GELU(u)  = u Phi(u) = max(u, 0) - |u| q,
+//   GELU'(u) = Phi(u) + u phi(u),  phi(u) = exp(-u^2/2) / sqrt(2 pi) (the same exponential).
+// q is formed directly (no 1 - erf cancellation for u < 0); one exponential and one
+// reciprocal per value.  Coefficients below: a_k / 2 and p / sqrt(2).
+__device__ __forceinline__ void gelu_tail(float u, float &q, float &e)
+{
+    const float s = __builtin_amdgcn_rcpf(fmaf(0.23164189f, fabsf(u), 1.0f));
+    const float hp = fmaf(s, fmaf(s, fmaf(s, fmaf(s, 0.5307027145f, -0.7265760135f), 0.7107068705f), -0.142248368f),
+                          0.127414796f);
+    e = __builtin_amdgcn_exp2f(u * (u * -0.72134752044448170f));  // exp(-u^2 / 2)
+    q = s * hp * e;
+}
 __device__ __forceinline__ void gelu_as(float u, float &g, float &dg)
 {
-    const float x = u * 0.70710678118654752f;
-    const float ax = fabsf(x);
-    const float s = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
-    const float poly =
-        s * fmaf(s, fmaf(s, fmaf(s, fmaf(s, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
-    const float e = __expf(-ax * ax);
-    const float erf_ax = fmaf(-poly, e, 1.0f);
-    const float erfx = __builtin_copysignf(erf_ax, x);
-    const float phi_cdf = fmaf(0.5f, erfx, 0.5f);
-    g = u * phi_cdf;
-    dg = fmaf(u * 0.39894228040143268f, e, phi_cdf);
+    float q, e;
+    gelu_tail(u, q, e);
+    g = fmaf(-fabsf(u), q, fmaxf(u, 0.0f));
+    dg = fmaf(u * 0.39894228040143268f, e, u >= 0.0f ? 1.0f - q : q);
 }
 __device__ __forceinline__ float gelu_fast(float u)
 {
-    float g, dg;
-    gelu_as(u, g, dg);
-    return g;
+    float q, e;
+    gelu_tail(u, q, e);
+    return fmaf(-fabsf(u), q, fmaxf(u, 0.0f));
 }
 __device__ __forceinline__ float gelu_grad_fast(float u)
 {
-    float g, dg;
-    gelu_as(u, g, dg);
-    return dg;
+    float q, e;
+    gelu_tail(u, q, e);
+    return fmaf(u * 0.39894228040143268f, e, u >= 0.0f ? 1.0f - q : q);
 }
 
 }  // namespace fno
