@@ -201,7 +201,8 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), g = lane >> 4, c = lane & 15;
     const int Nz = a.Nz, Nt = a.Nt, Kt = a.Kt, Kzp = a.Kzp, Cs = a.Cs, Csrc = a.Csrc, Csp = a.Csp;
     const int ZG = a.ZG, NT = a.NT, R = a.R, ldT = a.ldT, KK = a.Kz * Kt;
-    const bool has_src = PW && Csrc > 0;
+    // BLOCK and BWD always have a pointwise source (the host checks); ADJ may have none
+    const bool has_src = PW && (EPI == ZEPI_BLOCK || EPI == ZEPI_BWD || Csrc > 0);
     const long long nxy = (long long)a.Nx * a.Ny, plane = (long long)Nz * Nt, ncell = nxy * plane;
 
     // V rows hold 16 NTT values; the 4-value chunks of row r are stored XOR-swizzled by vswz(r)
@@ -321,6 +322,12 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
         const long long ei = ec + (long long)z0 * Nt;
 #pragma unroll
         for (int mt = 0; mt < NTQ; mt++) e[mt] = op_zero<T>();
+        // wave-uniform fast path (z0 is uniform): the whole group lies inside the grid
+        if (want && z0 + ZG <= Nz && 16 * NTQ == Nt) {
+            if constexpr (NTQ == 2) load8(base + ei, e[0], e[1]);
+            else e[0] = *reinterpret_cast<const Op *>(base + ei);
+            return;
+        }
         bool whole = false;
         if constexpr (NTQ == 2) {
             whole = want && zin && 8 * g + 8 <= Nt;
@@ -521,7 +528,6 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                 float v[NTQ][4];
 #pragma unroll
                 for (int mt = 0; mt < NTQ; mt++) {
-                    const bool ok = zok && 4 * NTQ * g + 4 * mt < Nt;
 #pragma unroll
                     for (int r = 0; r < 4; r++) v[mt][r] = acc[mt][r];
                     if (EPI == ZEPI_BLOCK) {
@@ -530,7 +536,8 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                     } else if (EPI == ZEPI_BWD) {
 #pragma unroll
                         for (int r = 0; r < 4; r++) {
-                            v[mt][r] = ok ? op_get(ext_c[mt], r) * gelu_grad_fast(v[mt][r] + bj) : 0.f;
+                            // gy is zero outside the grid (load_ext), so no select is needed
+                            v[mt][r] = op_get(ext_c[mt], r) * gelu_grad_fast(v[mt][r] + bj);
                             gbacc += v[mt][r];
                         }
                         acc[mt] = f4v{v[mt][0], v[mt][1], v[mt][2], v[mt][3]};  // gradient tile, B of the product below
@@ -540,15 +547,20 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                     }
                 }
                 T *op = out + ecol + (long long)z0 * Nt;
-                bool whole = false;
-                if constexpr (NTQ == 2) {
-                    whole = zok && 8 * g + 8 <= Nt;
-                    if (whole) store8(op, v);
-                }
-                if (!whole) {
+                if (z0 + ZG <= Nz && 16 * NTQ == Nt) {  // wave-uniform: the whole group is in the grid
+                    if constexpr (NTQ == 2) store8(op, v);
+                    else store4(op, v[0]);
+                } else {
+                    bool whole = false;
+                    if constexpr (NTQ == 2) {
+                        whole = zok && 8 * g + 8 <= Nt;
+                        if (whole) store8(op, v);
+                    }
+                    if (!whole) {
 #pragma unroll
-                    for (int mt = 0; mt < NTQ; mt++)
-                        if (zok && 4 * NTQ * g + 4 * mt < Nt) store4(op + 4 * mt, v[mt]);
+                        for (int mt = 0; mt < NTQ; mt++)
+                            if (zok && 4 * NTQ * g + 4 * mt < Nt) store4(op + 4 * mt, v[mt]);
+                    }
                 }
                 if (EPI == ZEPI_BWD) {
                     // C[(z', i) = 16 (qlo + s) + 4 g + r][n] += sum_t x[z'][i][t] gz[n][t]; K chunk = t tile mt
@@ -573,7 +585,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                     // gi is the same in every chunk: hide that, or the LDS addresses of all JM
                     // tiles are hoisted out of the chunk loop and held in registers throughout
                     int gi = tr + j * R;
-                    asm volatile("" : "+v"(gi));
+                    asm volatile("" : "+s"(gi));
                     if (gi < ngroups) {
                         const int z0 = zc0 + gi * ZG;
                         if (z0 < Nz) tile(gi, z0, ext[j]);
@@ -792,7 +804,8 @@ static hipError_t launch_zt_t(const Dims &d, int Cs, int Csrc, int accumulate, c
     if (lds == 0) return hipErrorInvalidValue;
     a.accumulate = accumulate;
     const int nth = 64 * a.NT * a.R;
-    if (a.NT * a.R > MAXW || a.NTQ != NTQ || (EPI != ZEPI_PLAIN && a.SPAN != SPAN && Csrc > 0))
+    if (a.NT * a.R > MAXW || a.NTQ != NTQ || (EPI != ZEPI_PLAIN && a.SPAN != SPAN && Csrc > 0) ||
+        ((EPI == ZEPI_BLOCK || EPI == ZEPI_BWD) && Csrc <= 0))
         return hipErrorInvalidValue;
     const void *kern = ZtKernel<EPI, T, NTT, NTQ, SPAN, split, MAXW>::get();
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
