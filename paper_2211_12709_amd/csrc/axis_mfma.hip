@@ -27,6 +27,34 @@ struct AxisArgs {
     int CB;           // columns per workgroup (k_axis_syn)
 };
 
+// Stage in[n][col0 + cl] (n < Nin, cl < CB = 2^lcb) into LDS as sl[cl][(re/im, n)], zero padded.
+// Consecutive threads read consecutive columns of one row; every thread issues UB loads before
+// its LDS writes, so a workgroup waits for one round of loads per UB rows, not one per row.
+template <typename TC>
+__device__ __forceinline__ void axis_stage(const float2 *__restrict__ src, long long cols, long long col0, int Nin,
+                                           int Ninp, int lcb, int ldk, TC *sl)
+{
+    constexpr int UB = 8;
+    const int total = Ninp << lcb, cmask = (1 << lcb) - 1;
+    for (int e0 = threadIdx.x; e0 < total; e0 += UB * 256) {
+        float2 v[UB];
+#pragma unroll
+        for (int k = 0; k < UB; k++) {
+            const int e = e0 + k * 256, n = e >> lcb, cl = e & cmask;
+            v[k] = (e < total && n < Nin && col0 + cl < cols) ? src[(long long)n * cols + col0 + cl]
+                                                               : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int k = 0; k < UB; k++) {
+            const int e = e0 + k * 256, n = e >> lcb, cl = e & cmask;
+            if (e < total) {
+                sl[cl * ldk + n] = from_f32<TC>(v[k].x);
+                sl[cl * ldk + Ninp + n] = from_f32<TC>(v[k].y);
+            }
+        }
+    }
+}
+
 template <typename TC, bool OUT16>
 __global__ void __launch_bounds__(256) k_axis_mfma(const float2 *__restrict__ in, void *__restrict__ out_,
                                                    const typename OpOf<TC>::type *__restrict__ tab,
@@ -42,14 +70,7 @@ __global__ void __launch_bounds__(256) k_axis_mfma(const float2 *__restrict__ in
     const int ldk = 2 * a.Ninp + 4;
     TC *sl = reinterpret_cast<TC *>(smem);  // [64 cols][(re/im, n)]
     const float2 *src = in + o * a.Nin * a.cols;
-    // stage: consecutive threads read consecutive columns of one row n
-    for (int e = threadIdx.x; e < a.Ninp * 64; e += 256) {
-        const int n = e / 64, cl = e % 64;
-        float2 v = make_float2(0.f, 0.f);
-        if (n < a.Nin && col0 + cl < a.cols) v = src[(long long)n * a.cols + col0 + cl];
-        sl[cl * ldk + n] = from_f32<TC>(v.x);
-        sl[cl * ldk + a.Ninp + n] = from_f32<TC>(v.y);
-    }
+    axis_stage<TC>(src, a.cols, col0, a.Nin, a.Ninp, 6, ldk, sl);
     __syncthreads();
     const int cl = 16 * w + c;  // this wave's column tile, lane column
     const long long col = col0 + cl;
@@ -59,15 +80,34 @@ __global__ void __launch_bounds__(256) k_axis_mfma(const float2 *__restrict__ in
     for (int mp = 0; mp < half; mp++) {
         // row tiles mp (re rows) and mp + half (im rows)
         f4v accr = f4_zero(), acci = f4_zero();
-        for (int q = 0; q < a.QK; q++) {
-            const Op bv = *reinterpret_cast<const Op *>(sl + cl * ldk + 16 * q + 4 * g);
-            const int ir = (mp * a.QK + q) * 64 + lane, ii = ((mp + half) * a.QK + q) * 64 + lane;
-            accr = mma16(tab[ir], bv, accr);
-            acci = mma16(tab[ii], bv, acci);
-            if (SPLIT) {
-                accr = mma16(tab_lo[ir], bv, accr);
-                acci = mma16(tab_lo[ii], bv, acci);
-            }
+        // QB K chunks at a time: all of their table loads are issued before the first product,
+        // so the wave waits for one round of loads per QB chunks instead of one per chunk
+        constexpr int QB = 4;
+        for (int q0 = 0; q0 < a.QK; q0 += QB) {
+            Op tr[QB], ti[QB], trl[QB], til[QB], bv[QB];
+#pragma unroll
+            for (int k = 0; k < QB; k++)
+                if (q0 + k < a.QK) {
+                    const int q = q0 + k;
+                    const int ir = (mp * a.QK + q) * 64 + lane, ii = ((mp + half) * a.QK + q) * 64 + lane;
+                    tr[k] = tab[ir];
+                    ti[k] = tab[ii];
+                    if (SPLIT) {
+                        trl[k] = tab_lo[ir];
+                        til[k] = tab_lo[ii];
+                    }
+                    bv[k] = *reinterpret_cast<const Op *>(sl + cl * ldk + 16 * q + 4 * g);
+                }
+#pragma unroll
+            for (int k = 0; k < QB; k++)
+                if (q0 + k < a.QK) {
+                    accr = mma16(tr[k], bv[k], accr);
+                    acci = mma16(ti[k], bv[k], acci);
+                    if (SPLIT) {
+                        accr = mma16(trl[k], bv[k], accr);
+                        acci = mma16(til[k], bv[k], acci);
+                    }
+                }
         }
 #pragma unroll
         for (int r = 0; r < 4; r++) {
@@ -102,14 +142,7 @@ __global__ void __launch_bounds__(256) k_axis_syn(const float2 *__restrict__ in,
     const int ldk = 2 * a.Ninp + 4;
     TC *sl = reinterpret_cast<TC *>(smem);  // [CB cols][(re/im, n)]
     const float2 *src = in + o * a.Nin * a.cols;
-    // stage: consecutive threads read consecutive columns of one row n
-    for (int e = threadIdx.x; e < a.Ninp * CB; e += 256) {
-        const int n = e / CB, cl = e % CB;
-        float2 v = make_float2(0.f, 0.f);
-        if (n < a.Nin && col0 + cl < a.cols) v = src[(long long)n * a.cols + col0 + cl];
-        sl[cl * ldk + n] = from_f32<TC>(v.x);
-        sl[cl * ldk + a.Ninp + n] = from_f32<TC>(v.y);
-    }
+    axis_stage<TC>(src, a.cols, col0, a.Nin, a.Ninp, __builtin_ctz(CB), ldk, sl);
     __syncthreads();
     float2 *dst = reinterpret_cast<float2 *>(out_) + o * a.Nout * a.cols;
     s2v *dst16 = reinterpret_cast<s2v *>(out_) + o * a.Nout * a.cols;
