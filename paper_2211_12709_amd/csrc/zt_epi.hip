@@ -33,7 +33,9 @@
 
 namespace fno {
 
-enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3 };
+// ZEPI_ADJ_ACC: EPI_ADJ adding into the existing output (a kernel of its own, so that the plain
+// adjoint holds no operand registers for it)
+enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3, ZEPI_ADJ_ACC = 4 };
 
 // Tuning knobs of the launch (defaults are the measured best on MI355X).
 #ifndef FNO_ZT_AHEAD_BWD
@@ -194,6 +196,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
 {
     typedef typename OpOf<T>::type Op;
     constexpr bool PW = EPI != ZEPI_PLAIN;
+    constexpr bool ADJ = EPI == ZEPI_ADJ || EPI == ZEPI_ADJ_ACC;
     constexpr int ZC = 16;  // z values per chunk
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int NTH = blockDim.x, NW = NTH >> 6;
@@ -243,7 +246,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
             float x = 0.f;
             if (s < nq && zs == zr && ci < Csrc)
                 // BLOCK/BWD: co = o, ci = i: W_pw[o][i];  ADJ: co = i, ci = o: W_pw[o][i]
-                x = EPI == ZEPI_ADJ ? wpw[ci * Cs + co] : wpw[co * Csrc + ci];
+                x = ADJ ? wpw[ci * Cs + co] : wpw[co * Csrc + ci];
             v[jj] = x;
         }
         wd[s] = op_from4<T>(v[0], v[1], v[2], v[3]);
@@ -273,7 +276,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     const bool u_ok = u_one ? (int)threadIdx.x < u_cstep * KK : true;
     // vector staging when Kt % 4 == 0: 16-byte (bfloat16) or 32-byte (float) items (not in the
     // bfloat16 EPI_BWD / EPI_ADJ kernels, whose register budget it overruns)
-    constexpr bool U_VEC = !(sizeof(T) == 2 && (EPI == ZEPI_BWD || EPI == ZEPI_ADJ));
+    constexpr bool U_VEC = !(sizeof(T) == 2 && (EPI == ZEPI_BWD || ADJ));
     const bool u_vec = U_VEC && Kt % 4 == 0;
     const int KK4 = KK / 4, nu4 = Cs * KK4;
     // source staging: item (channel quad cq, z zl, t quad t4) loads 4 consecutive t of channels
@@ -283,7 +286,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     constexpr int LT4 = NTQ == 2 ? 3 : 2;
     // (The bfloat16 EPI_BWD kernel measures faster with one item at a time over the Nt / 4 quads.)
     constexpr bool SRC_SEQ = sizeof(T) == 2 && EPI == ZEPI_BWD;
-    constexpr int SB = (sizeof(T) == 2 && EPI == ZEPI_ADJ) ? FNO_ZT_SBATCH_EXT : FNO_ZT_SBATCH;
+    constexpr int SB = (sizeof(T) == 2 && ADJ) ? FNO_ZT_SBATCH_EXT : FNO_ZT_SBATCH;
     const int nitem = ((Csrc + 3) / 4) << (LT4 + 4);
     const int nt4 = Nt / 4, npair = ZC * nt4, nitem_seq = npair * ((Csrc + 3) / 4);
     auto put_item = [&](int cq, int zl, int t4, const Op (&v)[4]) {
@@ -311,13 +314,13 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     // The epilogue operand (gy for EPI_BWD, the accumulated output for EPI_ADJ).  bfloat16 (AHEAD):
     // group j of this wave has its operand loaded one z chunk ahead into ext[j] (the host keeps
     // the groups per wave within JM); float: one tile ahead.
-    constexpr bool EXT = EPI == ZEPI_BWD || EPI == ZEPI_ADJ;
+    constexpr bool EXT = EPI == ZEPI_BWD || EPI == ZEPI_ADJ_ACC;
     constexpr bool AHEAD = EXT && sizeof(T) == 2 && (EPI != ZEPI_BWD || FNO_ZT_AHEAD_BWD);
     constexpr int JM = AHEAD ? 4 : 1;
     Op ext[JM][NTQ];
     auto load_ext = [&](long long ec, int z0, Op(&e)[NTQ]) {
         const T *base = EPI == ZEPI_BWD ? gy : out;
-        const bool want = EPI == ZEPI_BWD || (EPI == ZEPI_ADJ && a.accumulate);
+        constexpr bool want = EXT;
         const bool zin = z0 < Nz && z0 + zr < Nz;
         const long long ei = ec + (long long)z0 * Nt;
 #pragma unroll
@@ -541,7 +544,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                             gbacc += v[mt][r];
                         }
                         acc[mt] = f4v{v[mt][0], v[mt][1], v[mt][2], v[mt][3]};  // gradient tile, B of the product below
-                    } else if (EPI == ZEPI_ADJ) {
+                    } else if (EPI == ZEPI_ADJ_ACC) {
 #pragma unroll
                         for (int r = 0; r < 4; r++) v[mt][r] += op_get(ext_c[mt], r);
                     }
@@ -670,6 +673,7 @@ FNO_ZT_KERNEL(k_zt_plain, ZEPI_PLAIN)
 FNO_ZT_KERNEL(k_zt_block, ZEPI_BLOCK)
 FNO_ZT_KERNEL(k_zt_bwd, ZEPI_BWD)
 FNO_ZT_KERNEL(k_zt_adj, ZEPI_ADJ)
+FNO_ZT_KERNEL(k_zt_adj_acc, ZEPI_ADJ_ACC)
 #undef FNO_ZT_KERNEL
 
 template <int EPI, typename T, int NTT, int NTQ, int SPAN, bool SPLIT, int MAXW> struct ZtKernel;
@@ -682,6 +686,7 @@ FNO_ZT_PICK(k_zt_plain, ZEPI_PLAIN)
 FNO_ZT_PICK(k_zt_block, ZEPI_BLOCK)
 FNO_ZT_PICK(k_zt_bwd, ZEPI_BWD)
 FNO_ZT_PICK(k_zt_adj, ZEPI_ADJ)
+FNO_ZT_PICK(k_zt_adj_acc, ZEPI_ADJ_ACC)
 #undef FNO_ZT_PICK
 
 // ---------------------------------------------------------------- launcher
@@ -702,7 +707,7 @@ static int gcd_int(int a, int b)
 static size_t al16(size_t v) { return (v + 15) / 16 * 16; }
 
 // Geometry and LDS carve-up of one launch; returns the LDS bytes (0: shape not supported).
-static bool zt_ext(int epi) { return epi == ZEPI_BWD || epi == ZEPI_ADJ; }
+static bool zt_ext(int epi) { return epi == ZEPI_BWD || epi == ZEPI_ADJ_ACC; }
 
 static int zt_target_waves(int epi, int elem)
 {
@@ -771,7 +776,7 @@ static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, int target, b
 
 static bool zt_pair_ok(const Dims &d, int Cs, int Csrc, int elem)
 {
-    for (int epi = ZEPI_PLAIN; epi <= ZEPI_ADJ; epi++) {
+    for (int epi = ZEPI_PLAIN; epi <= ZEPI_ADJ_ACC; epi++) {
         ZtArgs a;
         const size_t lds = zt_layout(d, Cs, Csrc, elem, zt_target_waves(epi, elem), zt_ext(epi), a);
         if (lds == 0 || lds > 160 * 1024) return false;
@@ -835,6 +840,7 @@ hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const void *u, T 
                      const float *wpw, const float *bpw, float *part, const ZtTabs &tb, int accumulate, hipStream_t st,
                      int *rows_used)
 {
+    if (epi == ZEPI_ADJ && accumulate) epi = ZEPI_ADJ_ACC;
     ZtArgs a;
     if (zt_layout(d, Cs, Csrc, sizeof(T), zt_target_waves(epi, sizeof(T)), zt_ext(epi), a) == 0)
         return hipErrorInvalidValue;
@@ -864,7 +870,8 @@ hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const void *u, T 
     case ZEPI_PLAIN: FNO_ZT(ZEPI_PLAIN);
     case ZEPI_BLOCK: FNO_ZT(ZEPI_BLOCK);
     case ZEPI_BWD: FNO_ZT(ZEPI_BWD);
-    default: FNO_ZT(ZEPI_ADJ);
+    case ZEPI_ADJ: FNO_ZT(ZEPI_ADJ);
+    default: FNO_ZT(ZEPI_ADJ_ACC);
     }
 #undef FNO_ZT_W
 #undef FNO_ZT

@@ -172,6 +172,37 @@ def test_block_without_bias_and_accumulate(fno, o):
     assert rel(to_np(gwpw), gwpw_ref - 1.0) < F32_TOL
 
 
+@pytest.mark.parametrize("name", ["ns_shape_small", "long_t_plane"])
+@pytest.mark.parametrize("dt", [0, 1], ids=["f32", "bf16"])
+def test_accumulate_on_matrix_core_path(fno, o, name, dt):
+    """accumulate=True adds every gradient into the given buffers on the matrix-core z,t path
+    (Nt a multiple of 4), for the block and for the spectral layer alone."""
+    (B, Ci, Co, grid, modes), x, w, wpw, bpw, gy = case(name, dt, seed=9)
+    say(f"accumulate {name} dtype={dt}")
+    d = o.Dims(B, Ci, Co, grid, modes)
+    plan = fno.Plan(B, Ci, Co, grid, modes, dt)
+    xq, gyq = dev_act(x, plan.act_dtype), dev_act(gy, plan.act_dtype)
+    tw, twp, tb = (torch.from_numpy(a).cuda() for a in (w, wpw, bpw))
+    cache = plan.new_cache()
+    plan.block_fwd(xq, tw, twp, tb, cache=cache)
+    gx0 = torch.full_like(xq, 0.25)
+    gw0 = torch.full((Ci, Co, *d.kshape), 0.5 + 0.5j, dtype=torch.complex64, device="cuda")
+    gwpw0 = torch.full((Co, Ci), -1.0, device="cuda")
+    gb0 = torch.full((Co,), 2.0, device="cuda")
+    gx, gw, gwpw, gb = plan.block_bwd(xq, cache, tw, twp, tb, gyq, gx=gx0.clone(), gw=gw0.clone(),
+                                      gw_pw=gwpw0.clone(), gb_pw=gb0.clone(), accumulate=True)
+    gxs, gws = plan.spectral_bwd(gyq, tw, x=xq, gx=gx0.clone(), gw=gw0.clone(), accumulate=True)
+    torch.cuda.synchronize()
+    gx_ref, gw_ref, gwpw_ref, gb_ref = o.block_bwd(d, x, w, wpw, bpw, gy)
+    gxs_ref, gws_ref = o.spectral_bwd(d, x, w, gy)
+    errs = dict(gx=rel(to_np(gx), gx_ref + 0.25), gw=rel(to_np(gw), gw_ref + (0.5 + 0.5j)),
+                gw_pw=rel(to_np(gwpw), gwpw_ref - 1.0), gb=rel(to_np(gb), gb_ref + 2.0),
+                spectral_gx=rel(to_np(gxs), gxs_ref + 0.25), spectral_gw=rel(to_np(gws), gws_ref + (0.5 + 0.5j)))
+    say("  rel " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v < tol(dt), (k, v)
+
+
 def test_adjoint_dot_product_on_gpu(fno):
     """<S u, v> = <u, S* v> for the spectral layer, with both sides from the GPU."""
     B, Ci, Co, grid, modes = SHAPES["odd_ragged"]
