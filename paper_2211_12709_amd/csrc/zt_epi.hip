@@ -48,7 +48,7 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3, ZEPI_ADJ_ACC 
 #define FNO_ZT_SBATCH 2  // source staging items loaded together per thread
 #endif
 #ifndef FNO_ZT_SBATCH_EXT
-#define FNO_ZT_SBATCH_EXT 1  // the same for the bfloat16 ADJ kernel
+#define FNO_ZT_SBATCH_EXT 1  // the same for the bfloat16 accumulating ADJ kernel
 #endif
 #ifndef FNO_ZT_UBATCH
 #define FNO_ZT_UBATCH 2  // bfloat16 U staging items loaded together per thread (float: half)
@@ -275,8 +275,8 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     const int u_c0 = u_one ? (int)threadIdx.x / KK : 0;
     const bool u_ok = u_one ? (int)threadIdx.x < u_cstep * KK : true;
     // vector staging when Kt % 4 == 0: 16-byte (bfloat16) or 32-byte (float) items (not in the
-    // bfloat16 EPI_BWD / EPI_ADJ kernels, whose register budget it overruns)
-    constexpr bool U_VEC = !(sizeof(T) == 2 && (EPI == ZEPI_BWD || ADJ));
+    // bfloat16 accumulating EPI_ADJ kernel, whose register budget it overruns)
+    constexpr bool U_VEC = !(sizeof(T) == 2 && EPI == ZEPI_ADJ_ACC);
     const bool u_vec = U_VEC && Kt % 4 == 0;
     const int KK4 = KK / 4, nu4 = Cs * KK4;
     // source staging: item (channel quad cq, z zl, t quad t4) loads 4 consecutive t of channels
@@ -284,11 +284,8 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     // Items run over 4 NTQ t quads (a power of two; quads at or past Nt idle), so the item index
     // splits by shifts; SB items per thread have their loads issued before their writes.
     constexpr int LT4 = NTQ == 2 ? 3 : 2;
-    // (The bfloat16 EPI_BWD kernel measures faster with one item at a time over the Nt / 4 quads.)
-    constexpr bool SRC_SEQ = sizeof(T) == 2 && EPI == ZEPI_BWD;
-    constexpr int SB = (sizeof(T) == 2 && ADJ) ? FNO_ZT_SBATCH_EXT : FNO_ZT_SBATCH;
+    constexpr int SB = (sizeof(T) == 2 && EPI == ZEPI_ADJ_ACC) ? FNO_ZT_SBATCH_EXT : FNO_ZT_SBATCH;
     const int nitem = ((Csrc + 3) / 4) << (LT4 + 4);
-    const int nt4 = Nt / 4, npair = ZC * nt4, nitem_seq = npair * ((Csrc + 3) / 4);
     auto put_item = [&](int cq, int zl, int t4, const Op (&v)[4]) {
         Op r[4];
         op_transpose4(v, r);
@@ -395,20 +392,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
             __syncthreads();  // U staged / previous chunk's V and source consumed
             if (EXT && !AHEAD) load_ext(ecol, zc0 + tr * ZG, ext[0]);
             // source chunk -> LDS transposed [t][(zl, ci)]
-            if (SRC_SEQ && has_src) {
-                for (int e = threadIdx.x; e < nitem_seq; e += NTH) {
-                    const int pr = e % npair, cq = e / npair, zl = pr / nt4, t4 = pr - zl * nt4;
-                    const T *sp = srcp + (long long)(zc0 + zl) * Nt + 4 * t4;
-                    Op v[4];
-#pragma unroll
-                    for (int k = 0; k < 4; k++) {
-                        const int ci = 4 * cq + k;
-                        v[k] = (zc0 + zl < Nz && ci < Csrc) ? *reinterpret_cast<const Op *>(sp + (long long)ci * ncell)
-                                                            : op_zero<T>();
-                    }
-                    put_item(cq, zl, t4, v);
-                }
-            } else if (has_src) {
+            if (has_src) {
                 for (int e0 = threadIdx.x; e0 < nitem; e0 += SB * NTH) {
                     Op v[SB][4];
 #pragma unroll
