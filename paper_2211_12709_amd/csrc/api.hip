@@ -121,9 +121,6 @@ class KernelTimer {
         call;                        \
     } while (0)
 
-template <typename T> static const char *tname();
-template <> const char *tname<float>() { return "f32"; }
-template <> const char *tname<__bf16>() { return "bf16"; }
 
 static int dims_from_desc(const fno_desc_t *s, Dims *d)
 {

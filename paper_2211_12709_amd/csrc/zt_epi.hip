@@ -41,6 +41,9 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3, ZEPI_ADJ_ACC 
 #ifndef FNO_ZT_AHEAD_BWD
 #define FNO_ZT_AHEAD_BWD 0  // bfloat16 BWD: epilogue operands one z chunk ahead (else one tile)
 #endif
+#ifndef FNO_ZT_TZREG_BLOCK
+#define FNO_ZT_TZREG_BLOCK 1  // bfloat16 BLOCK: z-basis fragments in registers
+#endif
 #ifndef FNO_ZT_TZREG_BWD
 #define FNO_ZT_TZREG_BWD 0  // bfloat16 BWD: z-basis fragments in registers
 #endif
@@ -299,7 +302,8 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     const int QH = a.QZ / 2;
     // bfloat16: the z-basis K chunks of a z chunk are held in registers when 2 Kzp / 16 <= QZM
     constexpr int QZM = 4;
-    const bool tz_reg = sizeof(T) == 2 && (EPI != ZEPI_BWD || FNO_ZT_TZREG_BWD) && a.QZ <= QZM;
+    const bool tz_reg = sizeof(T) == 2 && (EPI != ZEPI_BWD || FNO_ZT_TZREG_BWD) &&
+                        (EPI != ZEPI_BLOCK || FNO_ZT_TZREG_BLOCK) && a.QZ <= QZM;
     __syncthreads();
 
     const long long nplanes = (long long)a.B * nxy;
