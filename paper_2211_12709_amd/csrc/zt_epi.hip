@@ -47,6 +47,9 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3, ZEPI_ADJ_ACC 
 #ifndef FNO_ZT_TZREG_BWD
 #define FNO_ZT_TZREG_BWD 0  // bfloat16 BWD: z-basis fragments in registers
 #endif
+#ifndef FNO_ZT_ZC_BF16
+#define FNO_ZT_ZC_BF16 16  // z values per chunk in the bfloat16 kernels (8 or 16; 8 measured slower)
+#endif
 #ifndef FNO_ZT_SBATCH
 #define FNO_ZT_SBATCH 2  // source staging items loaded together per thread
 #endif
@@ -93,6 +96,7 @@ struct ZtArgs {
     int QZ;    // K chunks of the z synthesis: 2 Kzp / 16
     int NTQ;   // t tiles: ceil(Nt / 16)
     int ZG;    // z values per column group: 16 / gcd(Cs, 16)
+    int ZC;    // z values per chunk: 8 or 16 (a multiple of ZG)
     int NT;    // 16-column tiles per group: ZG Cs / 16
     int R;     // waves per tile index: NW = NT R
     int SPAN;  // source K chunks per tile (2 or 4; 1 with no source)
@@ -200,7 +204,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     typedef typename OpOf<T>::type Op;
     constexpr bool PW = EPI != ZEPI_PLAIN;
     constexpr bool ADJ = EPI == ZEPI_ADJ || EPI == ZEPI_ADJ_ACC;
-    constexpr int ZC = 16;  // z values per chunk
+    const int ZC = a.ZC, LZC = ZC == 8 ? 3 : 4;  // z values per chunk (8 or 16), log2
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int NTH = blockDim.x, NW = NTH >> 6;
     // the wave index is uniform: keep it (and the tile indices derived from it) in scalar registers
@@ -288,7 +292,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
     // splits by shifts; SB items per thread have their loads issued before their writes.
     constexpr int LT4 = NTQ == 2 ? 3 : 2;
     constexpr int SB = (sizeof(T) == 2 && EPI == ZEPI_ADJ_ACC) ? FNO_ZT_SBATCH_EXT : FNO_ZT_SBATCH;
-    const int nitem = ((Csrc + 3) / 4) << (LT4 + 4);
+    const int nitem = ((Csrc + 3) / 4) << (LT4 + LZC);
     auto put_item = [&](int cq, int zl, int t4, const Op (&v)[4]) {
         Op r[4];
         op_transpose4(v, r);
@@ -401,7 +405,8 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                     Op v[SB][4];
 #pragma unroll
                     for (int m = 0; m < SB; m++) {
-                        const int e = e0 + m * NTH, t4 = e & (4 * NTQ - 1), zl = (e >> LT4) & 15, cq = e >> (LT4 + 4);
+                        const int e = e0 + m * NTH, t4 = e & (4 * NTQ - 1), zl = (e >> LT4) & (ZC - 1),
+                                  cq = e >> (LT4 + LZC);
                         const T *sp = srcp + (long long)(zc0 + zl) * Nt + 4 * t4;
                         const bool ok = e < nitem && 4 * t4 < Nt && zc0 + zl < Nz;
 #pragma unroll
@@ -413,7 +418,8 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                     }
 #pragma unroll
                     for (int m = 0; m < SB; m++) {
-                        const int e = e0 + m * NTH, t4 = e & (4 * NTQ - 1), zl = (e >> LT4) & 15, cq = e >> (LT4 + 4);
+                        const int e = e0 + m * NTH, t4 = e & (4 * NTQ - 1), zl = (e >> LT4) & (ZC - 1),
+                                  cq = e >> (LT4 + LZC);
                         if (e < nitem && 4 * t4 < Nt) put_item(cq, zl, t4, v[m]);
                     }
                 }
@@ -475,9 +481,13 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                     }
                 }
                 // acc[r] = V^T[(ri, kt) = 16 mt + 4 g + r][z = zc0 + c]
+                // column c is z = 16 zg + c; the chunk keeps z = zc0 .. zc0 + ZC - 1
                 float v[4] = {acc[0], acc[1], acc[2], acc[3]};
-                const int vr = c * Cs + cs;
-                store4(vl + (size_t)vr * ldv + 16 * mt + 4 * (g ^ vswz(vr)), v);
+                const int zc = c - (zc0 & 15);
+                if (zc >= 0 && zc < ZC) {
+                    const int vr = zc * Cs + cs;
+                    store4(vl + (size_t)vr * ldv + 16 * mt + 4 * (g ^ vswz(vr)), v);
+                }
             }
             __syncthreads();
             // ---- phase 2: this wave's tile of group gi (first z0), epilogue operand ext_c
@@ -722,14 +732,15 @@ static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, int target, b
     a.QZ = 2 * a.Kzp / 16;
     a.NTQ = (d.N[3] + 15) / 16;
     a.ZG = 16 / gcd_int(Cs, 16);
+    a.ZC = (elem == 2 && a.ZG <= FNO_ZT_ZC_BF16) ? FNO_ZT_ZC_BF16 : 16;
     a.NT = a.ZG * Cs / 16;
     if (a.NT > kZtMaxWaves) return 0;
     // waves per tile index: about `target` waves in all (at most 16), never more than there are groups
-    a.R = std::max(1, std::min(16 / a.ZG, (target + a.NT - 1) / a.NT));
+    a.R = std::max(1, std::min(a.ZC / a.ZG, (target + a.NT - 1) / a.NT));
     const bool ahead = ext && elem == 2;
-    if (ahead) a.R = std::max(a.R, (16 / a.ZG + 3) / 4);
+    if (ahead) a.R = std::max(a.R, (a.ZC / a.ZG + 3) / 4);
     while (a.NT * a.R > kZtMaxWaves) a.R--;
-    if (ahead && (16 / a.ZG + a.R - 1) / a.R > 4) return 0;
+    if (ahead && (a.ZC / a.ZG + a.R - 1) / a.R > 4) return 0;
     int span = 1;
     for (int j = 0; j < a.NT && Csrc > 0; j++) {
         const int zlo = (16 * j) / Cs, zhi = (16 * j + 15) / Cs;
@@ -740,10 +751,10 @@ static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, int target, b
     a.SPAN = Csrc == 0 ? 1 : std::max(2, span);
     // row stride of the transposed source: every tile reads SPAN chunks from its first one, so
     // the last group's tiles read up to 16 (qlo + SPAN) columns past that group's start
-    int reach = 16 * a.Csp;
+    int reach = a.ZC * a.Csp;
     for (int j = 0; j < a.NT && Csrc > 0; j++) {
         const int qlo = ((16 * j) / Cs * a.Csp) / 16;
-        reach = std::max(reach, (16 - a.ZG) * a.Csp + 16 * (qlo + a.SPAN));
+        reach = std::max(reach, (a.ZC - a.ZG) * a.Csp + 16 * (qlo + a.SPAN));
     }
     // rows cover whole 16-column blocks (the chunk swizzle stays inside a block), and the row
     // stride is 8 words mod 32 (see the kernel's xsw)
@@ -755,7 +766,7 @@ static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, int target, b
     while (((size_t)a.uim_off * elem / 4) % 32 != 16) a.uim_off += 16 / elem;
     size_t off = al16(((size_t)a.uim_off + (size_t)Cs * a.Kt * a.Kzp) * elem);
     a.off_v = (int)off;
-    off += al16((size_t)16 * Cs * (16 * ntt) * elem);
+    off += al16((size_t)a.ZC * Cs * (16 * ntt) * elem);
     a.off_x = (int)off;
     if (Csrc) off += al16((size_t)16 * a.NTQ * a.ldT * elem);
     // the BWD reduction at the end reuses the front: [waves][span][4][64] slots + [waves][64]
