@@ -22,9 +22,10 @@
 //            synthesis and the pointwise 1x1 land in one accumulator, four consecutive t per lane.
 //            Wave w always computes tile j = w mod NT (of groups w / NT, w / NT + R, ...), so its
 //            column map, pointwise-weight fragments and EPI_BWD accumulators stay in registers.
-//   bfloat16: phase 1 takes the chunk's z-basis fragments from registers (one round of loads per
-//            chunk instead of a dependent load per K step), and EPI_BWD / EPI_ADJ load each
-//            tile's epilogue operand one z chunk ahead (across planes at the last chunk).
+//   bfloat16: in EPI_BLOCK / EPI_ADJ phase 1 takes the chunk's z-basis fragments from registers
+//            (one round of loads per chunk instead of a dependent load per K step); the
+//            accumulating adjoint loads each tile's accumulated output one z chunk ahead (across
+//            planes at the last chunk), EPI_BWD its gy one tile ahead.
 //   EPI_BWD  the gradient tile is then the B operand of
 //              C[(z', i)][(z, o)] += sum_t x[z'][i][t] gz[z][o][t];
 //            its z' = z entries, summed over z, are the pointwise-weight gradient.
