@@ -23,6 +23,7 @@ from __future__ import annotations
 import argparse
 import glob
 import hashlib
+import re
 import json
 import os
 import sys
@@ -127,14 +128,22 @@ KERNEL_SOURCES = {
 }
 
 
+def _code_only(text):
+    """Source text without comments and with whitespace collapsed: what the compiler sees."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_hash(label):
+    """Hash of the code (comments and layout excluded) of the sources kernel `label` is built from."""
     key = "zt" if label.startswith("zt_") else "tzy" if label.startswith("tzy") else None
     if key is None:
         return None
     h = hashlib.sha256()
     for f in KERNEL_SOURCES[key]:
-        with open(os.path.join(CSRC, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(CSRC, f), encoding="utf-8") as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
