@@ -84,7 +84,7 @@ typedef struct {
 typedef struct fno_plan fno_plan_t;
 
 /* Host-only check of a descriptor (no HIP call).  FNO_OK or FNO_ERR_INVALID_ARG
- * (or FNO_ERR_UNSUPPORTED for a dtype/flag this build does not provide). */
+ * (or FNO_ERR_UNSUPPORTED for a dtype/flag the library does not provide). */
 int fno_desc_validate(const fno_desc_t *desc);
 
 /* Create a plan on the current HIP device: validates `desc`, allocates the

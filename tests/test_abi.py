@@ -69,7 +69,7 @@ def test_valid_descriptors(fno, name, dtype):
     (dict(modes=(9, 4, 4, 4)), 1),            # 2 m_x > N_x
     (dict(modes=(4, 4, 4, 6)), 1),            # m_t > N_t/2 + 1
     (dict(dtype=7), 2), (dict(flags=1), 2),
-    (dict(C_in=65), 2),                       # beyond this build's channel limit
+    (dict(C_in=65), 2),                       # beyond the library's channel limit
 ])
 def test_invalid_descriptors(fno, bad, code):
     args = dict(B=1, C_in=8, C_out=8, grid=(16, 16, 16, 8), modes=(4, 4, 4, 4), dtype=0, flags=0)
