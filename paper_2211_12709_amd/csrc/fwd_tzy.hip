@@ -23,6 +23,13 @@
 #ifndef FNO_TZY_WAVES_BF16
 #define FNO_TZY_WAVES_BF16 2  // waves per SIMD the bfloat16 kernel is compiled for
 #endif
+#ifndef FNO_TZY_NW_BF16
+#define FNO_TZY_NW_BF16 8  // waves per workgroup of the bfloat16 kernel (the y-step tiles are split over them)
+#endif
+#ifndef FNO_TZY_NW_F32
+#define FNO_TZY_NW_F32 4  // the same for the float kernel
+#endif
+template <typename T> constexpr int tzy_nw() { return sizeof(T) == 2 ? FNO_TZY_NW_BF16 : FNO_TZY_NW_F32; }
 #ifndef FNO_TZY_WAVES_F32
 #define FNO_TZY_WAVES_F32 1  // the same for the float kernel
 #endif
@@ -38,7 +45,7 @@ struct TzyArgs {
 // MY: row tiles of the y step (2 ceil(Ky/16)); NBW: its column tiles per wave.
 // NZBM: max z blocks (Nz <= 16*NZBM); MAXKB: max kz blocks.
 template <typename T, int NTT, bool SPLIT, int MY, int NBW, int NZBM, int MAXKB>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 2 ? FNO_TZY_WAVES_BF16 : FNO_TZY_WAVES_F32))) k_tzy_fwd(const T *__restrict__ x, float2 *__restrict__ t2,
+__global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 2 ? FNO_TZY_WAVES_BF16 : FNO_TZY_WAVES_F32))) k_tzy_fwd(const T *__restrict__ x, float2 *__restrict__ t2,
                                                  const typename OpOf<T>::type *__restrict__ tabT,
                                                  const typename OpOf<T>::type *__restrict__ tabT_lo,
                                                  const typename OpOf<T>::type *__restrict__ tabZ,
@@ -59,7 +66,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     T *tl = reinterpret_cast<T *>(smem + sizeof(Op) * nzf * (SPLIT ? 2 : 1));
     const int ldk = 2 * a.Yc + 4;
     const int ncol = Kz * Kt;
-    for (int i = threadIdx.x; i < nzf; i += 256) {
+    constexpr int NW = tzy_nw<T>();
+    for (int i = threadIdx.x; i < nzf; i += 64 * NW) {
         zl[i] = tabZ[i];
         if (SPLIT) zl[nzf + i] = tabZ_lo[i];
     }
@@ -72,13 +80,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
             if (SPLIT) tbl[q][nt] = q < a.NQ ? tabT_lo[(q * NTT + nt) * 64 + lane] : op_zero<T>();
         }
 
-    f4v acc[NBW][MY];  // y-step tiles: column block w + 4 nbi, row block mb (re rows < MY/2 <= im rows)
+    f4v acc[NBW][MY];  // y-step tiles: column block w + NW nbi, row block mb (re rows < MY/2 <= im rows)
 #pragma unroll
     for (int nbi = 0; nbi < NBW; nbi++)
 #pragma unroll
         for (int mb = 0; mb < MY; mb++) acc[nbi][mb] = f4_zero();
     const int NT2 = (ncol + 15) / 16;
-    const int per_wave = a.Yc / 4;  // planes per wave per chunk
+    const int per_wave = a.Yc / NW;  // planes per wave per chunk
 
     // fragments of one plane: dst[zb][q] = x[y][zb*16 + c][16 q + 4 g .. + 3]
     auto load_plane = [&](int y, Op (&dst)[NZBM][2]) {
@@ -96,7 +104,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     __syncthreads();
 
     const int nplanes = a.NYC * per_wave;  // plane slots of this wave
-    auto plane_y = [&](int s) { return (s / per_wave) * a.Yc + (s % per_wave) * 4 + w; };
+    auto plane_y = [&](int s) { return (s / per_wave) * a.Yc + (s % per_wave) * NW + w; };
     // t and z steps of two planes (s, s + 1) at once: every z-basis fragment read
     // from LDS feeds both planes, and the two independent MFMA chains overlap.
     // Planes beyond Ny have zero input (guarded loads), hence a zero spectrum.
@@ -157,7 +165,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
         // combine cos/sin halves into the complex spectrum and stage it in LDS
 #pragma unroll
         for (int u = 0; u < 2; u++) {
-            const int yl = ((s + u) % per_wave) * 4 + w;
+            const int yl = ((s + u) % per_wave) * NW + w;
 #pragma unroll
             for (int kb = 0; kb < MAXKB; kb++) {
                 if (kb < a.KB) {
@@ -204,7 +212,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                 }
 #pragma unroll
                 for (int nbi = 0; nbi < NBW; nbi++) {
-                    const int nb = w + 4 * nbi;
+                    const int nb = w + NW * nbi;
                     if (nb < NT2) {
                         const int col = nb * 16 + c;
                         const Op bt = col < ncol ? *reinterpret_cast<const Op *>(tl + col * ldk + 16 * q + 4 * g)
@@ -240,7 +248,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     // write T2[slab][ky][(kz, kt)] as (re, im): row block mb holds re rows, mb + MY/2 the matching im rows
 #pragma unroll
     for (int nbi = 0; nbi < NBW; nbi++) {
-        const int nb = w + 4 * nbi;
+        const int nb = w + NW * nbi;
         if (nb < NT2) {
             const int col = nb * 16 + c;
 #pragma unroll
@@ -278,17 +286,18 @@ static hipError_t launch_tzy_t(const T *x, float2 *t2, long long slabs, const Tz
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)slabs), dim3(256), lds, st, x, t2, (const Op *)tb.t, (const Op *)tb.t_lo,
+    hipLaunchKernelGGL(kern, dim3((unsigned)slabs), dim3(64 * tzy_nw<T>()), lds, st, x, t2, (const Op *)tb.t, (const Op *)tb.t_lo,
                        (const Op *)tb.z, (const Op *)tb.z_lo, (const Op *)tb.y, (const Op *)tb.y_lo, a);
     return hipGetLastError();
 }
 
 // (row tiles, column tiles per wave) of the y step
-static void tzy_tiles(const Dims &d, int &MY, int &NBW)
+// nw: waves per workgroup of the kernel that will run
+static void tzy_tiles(const Dims &d, int nw, int &MY, int &NBW)
 {
     MY = 2 * ((d.K[1] + 15) / 16);
     const int NT2 = (d.K[2] * d.K[3] + 15) / 16;
-    NBW = (NT2 + 3) / 4;
+    NBW = (NT2 + nw - 1) / nw;
 }
 
 // Whether the MFMA path covers these dimensions.
@@ -297,7 +306,7 @@ bool tzy_supported(const Dims &d, int dtype)
     const int Nt = d.N[3], Nz = d.N[2];
     if (Nt % 4 != 0 || Nt > 32 || Nz > 128 || d.K[3] > 16 || d.K[2] > 32) return false;
     int MY, NBW;
-    tzy_tiles(d, MY, NBW);
+    tzy_tiles(d, dtype == FNO_BF16 ? FNO_TZY_NW_BF16 : FNO_TZY_NW_F32, MY, NBW);
     if (MY > 4 || NBW > 8) return false;
     TzyArgs a{};
     a.NZB = (Nz + 15) / 16;
@@ -332,10 +341,12 @@ template <typename T, int NTT>
 static hipError_t launch_tzy_n(const T *x, float2 *t2, long long slabs, const TzyTabs &tb, const TzyArgs &a, int MY,
                                int NBW, hipStream_t st)
 {
-    if (MY == 2) return NBW <= 4 ? launch_tzy_t<T, NTT, 2, 4>(x, t2, slabs, tb, a, st)
-                                 : launch_tzy_t<T, NTT, 2, 8>(x, t2, slabs, tb, a, st);
-    return NBW <= 4 ? launch_tzy_t<T, NTT, 4, 4>(x, t2, slabs, tb, a, st)
-                    : launch_tzy_t<T, NTT, 4, 8>(x, t2, slabs, tb, a, st);
+    if (MY == 2) return NBW <= 2   ? launch_tzy_t<T, NTT, 2, 2>(x, t2, slabs, tb, a, st)
+                       : NBW <= 4 ? launch_tzy_t<T, NTT, 2, 4>(x, t2, slabs, tb, a, st)
+                                  : launch_tzy_t<T, NTT, 2, 8>(x, t2, slabs, tb, a, st);
+    return NBW <= 2   ? launch_tzy_t<T, NTT, 4, 2>(x, t2, slabs, tb, a, st)
+           : NBW <= 4 ? launch_tzy_t<T, NTT, 4, 4>(x, t2, slabs, tb, a, st)
+                      : launch_tzy_t<T, NTT, 4, 8>(x, t2, slabs, tb, a, st);
 }
 
 template <typename T>
@@ -344,7 +355,7 @@ hipError_t launch_tzy(const T *x, float2 *t2, long long slabs, const TzyTabs &tb
     const int dtype = sizeof(T) == 2 ? FNO_BF16 : FNO_F32;
     const TzyArgs a = tzy_args(d, dtype);
     int MY, NBW;
-    tzy_tiles(d, MY, NBW);
+    tzy_tiles(d, tzy_nw<T>(), MY, NBW);
     if (d.K[3] <= 8) return launch_tzy_n<T, 1>(x, t2, slabs, tb, a, MY, NBW, st);
     return launch_tzy_n<T, 2>(x, t2, slabs, tb, a, MY, NBW, st);
 }
