@@ -46,6 +46,7 @@ WORKLOADS = {
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
 METRIC = "FNO block fwd+bwd ms/step & TFLOP/s, BF16 vs FP32 at stated rel err"
+REL_L2_TARGET = {"bf16": 1e-2, "f32": 1e-5}  # relative L2 error against the FP64 oracle, every output
 
 
 def log(msg):
@@ -166,6 +167,23 @@ def profiled_traffic(label, dtype, workload):
 
 
 # ------------------------------------------------------------------ helpers
+def median_ci(xs, level=0.95):
+    """Median of the per-step times and a distribution-free confidence interval for it: the
+    order statistics (x_(j), x_(n+1-j)) with the largest j whose binomial coverage is >= level."""
+    from math import comb
+    v = sorted(xs)
+    n = len(v)
+    med = float(np.median(v))
+    lo, hi = v[0], v[-1]
+    for j in range(1, n // 2 + 1):
+        cover = sum(comb(n, i) for i in range(j, n - j + 1)) / 2.0 ** n
+        if cover >= level:
+            lo, hi = v[j - 1], v[n - j]
+        else:
+            break
+    return med, float(lo), float(hi)
+
+
 def rel(a, ref):
     return float(np.linalg.norm((a - ref).ravel()) / max(np.linalg.norm(ref.ravel()), 1e-300))
 
@@ -219,23 +237,32 @@ def run_gpu(args, wl):
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
-        plan.timing(True)
-        plan.timing_read()
         log(f"[bench] {dt_name}: timing {args.steps} steps")
+        # headline: the K steps back to back, one event between consecutive steps (no per-kernel events)
         stream = torch.cuda.current_stream()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ev0.record(stream)
-        for _ in range(args.steps):
+        evs[0].record(stream)
+        for k in range(args.steps):
             step()
-        ev1.record(stream)
+            evs[k + 1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        per_step = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+        ms = evs[0].elapsed_time(evs[-1]) / args.steps
+        # per-kernel durations: a separate pass of the same steps with every launch bracketed by
+        # HIP events on its stream (the library's timing records)
+        plan.timing(True)
+        plan.timing_read()
+        for _ in range(args.kernel_steps):
+            step()
+        torch.cuda.synchronize()
         plan.timing(False)
         kern = plan.timing_read()
-        ms = ev0.elapsed_time(ev1) / args.steps
-        results[dt_name] = dict(ms=ms, wall_ms=wall * 1000 / args.steps, kernels=kern)
+        med, lo, hi = median_ci(per_step)
+        results[dt_name] = dict(ms=ms, wall_ms=wall * 1000 / args.steps, kernels=kern, median_ms=med,
+                                ci95_ms=[lo, hi], kernel_steps=args.kernel_steps)
         log(f"[bench] {dt_name}: {ms:.3f} ms/step")
         if not args.no_oracle:
             outputs[dt_name] = dict(y=y.float().cpu().numpy(), gx=gx.float().cpu().numpy(),
@@ -262,8 +289,10 @@ def run_oracle(wl, data):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=16)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--kernel-steps", type=int, default=4,
+                    help="steps of the separate pass whose kernels are timed one by one")
     ap.add_argument("--workload", default="co2_block_128^3x32", choices=sorted(WORKLOADS))
     ap.add_argument("--no-oracle", action="store_true", help="skip the FP64 oracle (errors and cpu_baseline)")
     ap.add_argument("--no-fp32", action="store_true", help="time the BF16 path only")
@@ -334,11 +363,20 @@ def main():
         "bf16_speedup_vs_fp32": (results["f32"]["ms"] / ms) if "f32" in results else None,
         "model_gflop_per_step": model_flops / 1e9,
         "rel_l2_vs_fp64_oracle": errs or None,
-        "kernels_ms_per_step": {dt: {k: v[1] / args.steps for k, v in r["kernels"].items()} for dt, r in results.items()},
+        "rel_l2_targets": REL_L2_TARGET,
+        "rel_l2_within_targets": (all(v <= REL_L2_TARGET[dt] for dt, e in errs.items() for v in e.values())
+                                  if errs else None),
+        "median_ms_per_step": {dt: r["median_ms"] for dt, r in results.items()},
+        "ci95_ms_per_step": {dt: r["ci95_ms"] for dt, r in results.items()},
+        "kernels_ms_per_step": {dt: {k: v[1] / r["kernel_steps"] for k, v in r["kernels"].items()}
+                                for dt, r in results.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+    if errs and not line["rel_l2_within_targets"]:
+        log(f"[bench] relative L2 error above target: {errs}")
+        sys.exit(3)
 
 
 if __name__ == "__main__":

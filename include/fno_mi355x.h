@@ -55,7 +55,7 @@ typedef enum {
     FNO_ERR_INVALID_ARG = 1, /* null pointer, non-positive size, mode count out of range  */
     FNO_ERR_UNSUPPORTED = 2, /* valid but not implemented (dtype, sizes beyond limits)    */
     FNO_ERR_ALIGNMENT = 3,   /* a tensor pointer not 16-byte aligned                       */
-    FNO_ERR_WORKSPACE = 4,   /* workspace or cache smaller than fno_workspace_bytes / fno_cache_bytes */
+    FNO_ERR_WORKSPACE = 4,   /* ws_bytes smaller than fno_workspace_bytes (or a too small text buffer) */
     FNO_ERR_HIP = 5,         /* HIP runtime or launch error                                */
     FNO_ERR_OOM = 6          /* device allocation failed (plan creation only)              */
 } fno_status_t;
@@ -97,7 +97,11 @@ int fno_plan_destroy(fno_plan_t *plan);
 /* Workspace bytes one call of operation `op` (FNO_OP_*) needs. */
 int fno_workspace_bytes(const fno_plan_t *plan, int op, size_t *out);
 /* Bytes of the forward cache (retained spectrum X^ and the x-inverse of Y^)
- * written by fno_spectral_fwd / fno_block_fwd and read by the backward calls. */
+ * written by fno_spectral_fwd / fno_block_fwd and read by the backward calls.
+ * Precondition of every entry point that takes a non-NULL `cache`: it points to
+ * at least this many bytes of device memory.  The entry points take no cache
+ * size, so the library cannot check this; a shorter buffer is written or read
+ * out of bounds on the device. */
 int fno_cache_bytes(const fno_plan_t *plan, size_t *out);
 
 /* Spectral convolution layer (Alg. 2): y = S(x; w).  cache (nullable)

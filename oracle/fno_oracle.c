@@ -644,50 +644,69 @@ void oracle_proj_fwd(int B, int Ci, int H, int Co, long N, const double *x, cons
     }
 }
 
-/* Backward of the projection; every output nullable, written (not added). */
+/* Backward of the projection; every output nullable, written (not added).
+ * The points are split into a fixed number of contiguous chunks; each chunk's
+ * weight-gradient sums run over its points in order, and the chunk sums are
+ * added in chunk order, so the result does not depend on the thread count. */
+#define PROJ_CHUNKS 256
 void oracle_proj_bwd(int B, int Ci, int H, int Co, long N, const double *x, const double *w1, const double *b1,
                      const double *w2, const double *b2, const double *gy, double *gx, double *gw1, double *gb1,
                      double *gw2, double *gb2)
 {
     (void)b2;
-    if (gw1) memset(gw1, 0, sizeof(double) * H * Ci);
-    if (gb1) memset(gb1, 0, sizeof(double) * H);
-    if (gw2) memset(gw2, 0, sizeof(double) * Co * H);
-    if (gb2) memset(gb2, 0, sizeof(double) * Co);
-    double *z = (double *)malloc(sizeof(double) * H), *gh = (double *)malloc(sizeof(double) * H);
-    /* one pass over points in a fixed order keeps the weight-gradient sums deterministic */
-    for (long b = 0; b < B; b++)
-        for (long p = 0; p < N; p++) {
-            for (long k = 0; k < H; k++) {
-                double acc = b1 ? b1[k] : 0.0;
-                for (long i = 0; i < Ci; i++) acc += w1[k * Ci + i] * x[((size_t)b * Ci + i) * N + p];
-                z[k] = acc;
-            }
-            for (long k = 0; k < H; k++) {
-                double g = 0;
-                for (long o = 0; o < Co; o++) g += w2[o * H + k] * gy[((size_t)b * Co + o) * N + p];
-                gh[k] = g * oracle_gelu_grad(z[k]);
-            }
-            for (long o = 0; o < Co; o++) {
-                const double g = gy[((size_t)b * Co + o) * N + p];
-                if (gb2) gb2[o] += g;
-                if (gw2)
-                    for (long k = 0; k < H; k++) gw2[o * H + k] += g * oracle_gelu(z[k]);
-            }
-            for (long k = 0; k < H; k++) {
-                if (gb1) gb1[k] += gh[k];
-                if (gw1)
-                    for (long i = 0; i < Ci; i++) gw1[k * Ci + i] += gh[k] * x[((size_t)b * Ci + i) * N + p];
-            }
-            if (gx)
-                for (long i = 0; i < Ci; i++) {
-                    double acc = 0;
-                    for (long k = 0; k < H; k++) acc += w1[k * Ci + i] * gh[k];
-                    gx[((size_t)b * Ci + i) * N + p] = acc;
+    const long np = (long)B * N;
+    const long per = (np + PROJ_CHUNKS - 1) / PROJ_CHUNKS;
+    const long len = (long)H * Ci + H + (long)Co * H + Co; /* gw1, gb1, gw2, gb2 of one chunk */
+    double *part = (double *)calloc((size_t)PROJ_CHUNKS * len, sizeof(double));
+    #pragma omp parallel
+    {
+        double *z = (double *)malloc(sizeof(double) * H), *gh = (double *)malloc(sizeof(double) * H);
+        #pragma omp for schedule(dynamic)
+        for (long ch = 0; ch < PROJ_CHUNKS; ch++) {
+            double *pw1 = part + (size_t)ch * len, *pb1 = pw1 + (size_t)H * Ci, *pw2 = pb1 + H, *pb2 = pw2 + (size_t)Co * H;
+            const long end = (ch + 1) * per < np ? (ch + 1) * per : np;
+            for (long e = ch * per; e < end; e++) {
+                const long b = e / N, p = e % N;
+                for (long k = 0; k < H; k++) {
+                    double acc = b1 ? b1[k] : 0.0;
+                    for (long i = 0; i < Ci; i++) acc += w1[k * Ci + i] * x[((size_t)b * Ci + i) * N + p];
+                    z[k] = acc;
                 }
+                for (long k = 0; k < H; k++) {
+                    double g = 0;
+                    for (long o = 0; o < Co; o++) g += w2[o * H + k] * gy[((size_t)b * Co + o) * N + p];
+                    gh[k] = g * oracle_gelu_grad(z[k]);
+                }
+                for (long o = 0; o < Co; o++) {
+                    const double g = gy[((size_t)b * Co + o) * N + p];
+                    pb2[o] += g;
+                    for (long k = 0; k < H; k++) pw2[o * H + k] += g * oracle_gelu(z[k]);
+                }
+                for (long k = 0; k < H; k++) {
+                    pb1[k] += gh[k];
+                    for (long i = 0; i < Ci; i++) pw1[k * Ci + i] += gh[k] * x[((size_t)b * Ci + i) * N + p];
+                }
+                if (gx)
+                    for (long i = 0; i < Ci; i++) {
+                        double acc = 0;
+                        for (long k = 0; k < H; k++) acc += w1[k * Ci + i] * gh[k];
+                        gx[((size_t)b * Ci + i) * N + p] = acc;
+                    }
+            }
         }
-    free(z);
-    free(gh);
+        free(z);
+        free(gh);
+    }
+    for (long j = 0; j < len; j++) {
+        double acc = 0;
+        for (long ch = 0; ch < PROJ_CHUNKS; ch++) acc += part[(size_t)ch * len + j];
+        double *dst = j < (long)H * Ci ? (gw1 ? gw1 + j : NULL)
+                      : j < (long)H * Ci + H ? (gb1 ? gb1 + (j - (long)H * Ci) : NULL)
+                      : j < (long)H * Ci + H + (long)Co * H ? (gw2 ? gw2 + (j - (long)H * Ci - H) : NULL)
+                      : (gb2 ? gb2 + (j - (long)H * Ci - H - (long)Co * H) : NULL);
+        if (dst) *dst = acc;
+    }
+    free(part);
 }
 
 /* Mean-squared-error loss L = (1/n) sum (y - t)^2 and its gradient gy = 2 (y - t)/n (nullable). */

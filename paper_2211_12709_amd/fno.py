@@ -149,12 +149,15 @@ class Plan:
         return n.value
 
     def workspace(self, op):
-        """A reusable workspace for `op` (one per plan and op; reused across calls on the current stream)."""
+        """A reusable workspace for `op` on the current stream: one per (op, stream), so calls that
+        share this plan on different streams never share a workspace, while the calls of one stream
+        (which run in order) reuse theirs."""
         n = self.workspace_bytes(op)
-        ws = self._ws.get(op)
+        key = (op, torch.cuda.current_stream().cuda_stream)
+        ws = self._ws.get(key)
         if ws is None or ws.numel() < n:
             ws = torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
-            self._ws[op] = ws
+            self._ws[key] = ws
         return ws
 
     def new_cache(self):
@@ -280,11 +283,12 @@ _glue_ws = {}
 def _glue_workspace(device, ci, h, co):
     n = _sz()
     _check(load_library().fno_glue_workspace_bytes(ci, h, co, ctypes.byref(n)), "fno_glue_workspace_bytes")
-    key = (device, n.value)
-    ws = _glue_ws.get(device)
+    # one workspace per (device, stream): calls on one stream run in order and may share it
+    key = (str(device), torch.cuda.current_stream(device).cuda_stream)
+    ws = _glue_ws.get(key)
     if ws is None or ws.numel() < n.value:
         ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=device)
-        _glue_ws[device] = ws
+        _glue_ws[key] = ws
     return ws
 
 

@@ -1,6 +1,11 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py
 times (same plans, same kernels):
 
+* the CO2-shaped block (128^3 x 32, width 20, modes 16,16,16,8, the benchmark
+  workload) fwd + bwd in FP32 and BF16 against the full FP64 oracle, run once
+  for both: relative L2 of y, gx, gw, gw_pw and gb (1e-5 / 1e-2) and a
+  per-element bound max|a - ref| <= c RMS(ref), which a single wrong
+  (b, c, x, y) plane (about 1/128 of the norm of one channel) would break;
 * the Navier-Stokes-shaped block (64^3 x 16, width 20, modes 12,12,12,8)
   fwd + bwd against the full FP64 oracle (every output element);
 * the CO2-shaped block (128^3 x 32, width 20, modes 16,16,16,8): sampled
@@ -103,3 +108,64 @@ def test_co2_block_sampled_modes_and_adjoint(fno, o):
     rhs = float((xq.double() * gx.double()).sum())
     print(f"<Su,v>={lhs:.6e} <u,S*v>={rhs:.6e}", flush=True)
     assert abs(lhs - rhs) <= 1e-5 * (abs(lhs) + abs(rhs))
+
+
+# ---------------------------------------------------------------- CO2-shaped block, whole tensors
+CO2 = (1, 20, (128, 128, 128, 32), (16, 16, 16, 8))
+
+
+@pytest.fixture(scope="module")
+def co2_ref(o):
+    """The benchmark's inputs (smooth seeded fields, seeded weights) and the FP64 oracle's block
+    fwd + bwd on them, computed once for both dtypes."""
+    B, C, grid, modes = CO2
+    d = o.Dims(B, C, C, grid, modes)
+    print("co2 128^3x32: inputs + FP64 oracle block fwd+bwd", flush=True)
+    x = inputs.smooth_spacetime_field(B, C, grid, seed=inputs.SEED_INPUT)
+    gy = inputs.smooth_spacetime_field(B, C, grid, seed=inputs.SEED_TARGET)
+    w, wpw, bpw = inputs.block_params(C, C, d.kshape, block=0)
+    y = o.block_fwd(d, x, w, wpw, bpw)
+    gx, gw, gwpw, gb = o.block_bwd(d, x, w, wpw, bpw, gy)
+    return dict(d=d, x=x, gy=gy, w=w, wpw=wpw, bpw=bpw,
+                ref=dict(y=y, gx=gx, gw=gw, gw_pw=gwpw, gb=gb))
+
+
+def errors(dev_t, ref):
+    """(relative L2, max|a - ref| / RMS(ref)) of a device tensor against an FP64 array, one
+    leading slice at a time (host memory stays at one channel's worth of float64)."""
+    num = den = 0.0
+    amax = 0.0
+    t = dev_t.detach()
+    lead = t.shape[0] * t.shape[1] if t.dim() >= 3 else 1
+    tv = t.reshape(lead, -1)
+    rv = np.asarray(ref).reshape(lead, -1)
+    for i in range(lead):
+        a = tv[i].cpu()
+        a = a.numpy().astype(np.complex128) if a.is_complex() else a.float().numpy().astype(np.float64)
+        diff = np.abs(a - rv[i])
+        num += float(np.sum(diff ** 2))
+        den += float(np.sum(np.abs(rv[i]) ** 2))
+        amax = max(amax, float(diff.max()))
+    rms = np.sqrt(den / rv.size)
+    return np.sqrt(num / den), amax / rms
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("code,tol,cmax", [(0, 1e-5, 1e-4), (1, 1e-2, 0.1)], ids=["f32", "bf16"])
+def test_co2_block_full_size(fno, o, co2_ref, code, tol, cmax):
+    B, C, grid, modes = CO2
+    print(f"co2 block 128^3x32 fwd+bwd dtype={code}", flush=True)
+    plan = fno.Plan(B, C, C, grid, modes, code)
+    xq = torch.from_numpy(co2_ref["x"]).cuda().to(plan.act_dtype)
+    gyq = torch.from_numpy(co2_ref["gy"]).cuda().to(plan.act_dtype)
+    tw, twp, tb = (torch.from_numpy(a).cuda() for a in (co2_ref["w"], co2_ref["wpw"], co2_ref["bpw"]))
+    cache = plan.new_cache()
+    y = plan.block_fwd(xq, tw, twp, tb, cache=cache)
+    gx, gw, gwpw, gb = plan.block_bwd(xq, cache, tw, twp, tb, gyq)
+    torch.cuda.synchronize()
+    got = dict(y=y, gx=gx, gw=gw, gw_pw=gwpw, gb=gb)
+    res = {k: errors(got[k], co2_ref["ref"][k]) for k in got}
+    print({k: f"rel {v[0]:.2e} max/rms {v[1]:.2e}" for k, v in res.items()}, flush=True)
+    for k, (e, m) in res.items():
+        assert e < tol, (k, e)
+        assert m < cmax, (k, m)

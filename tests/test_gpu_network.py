@@ -175,3 +175,57 @@ def test_network_finite_differences(fno, o):
     for c in checks:
         fd, an = c[-2], c[-1]
         assert abs(fd - an) <= 2e-3 * abs(fd) + 1e-4 * scale, c
+
+
+# ---------------------------------------------------------------- Navier-Stokes-shaped network at full size
+NS_GRID, NS_MODES, NS_WIDTH = (64, 64, 64, 16), (12, 12, 12, 8), 20
+
+
+@pytest.fixture(scope="module")
+def ns_full(o):
+    """The full Navier-Stokes-shaped FNO (4-channel input on 64^3 x 16, lifting to width 20,
+    4 blocks with modes 12,12,12,8, projection 20 -> 128 -> 1) and an MSE loss against a
+    seeded target: FP64 oracle forward (every block's output kept) and gradients, once."""
+    d = o.Dims(1, NS_WIDTH, NS_WIDTH, NS_GRID, NS_MODES)
+    params = ns_params(NS_WIDTH, d.kshape)
+    x = inputs.ns_like_input(1, NS_GRID)
+    target = inputs.normal_field((1, 1, *NS_GRID), seed=inputs.SEED_TARGET)
+    print("ns network 64^3x16: FP64 oracle forward + backward", flush=True)
+    y_ref, acts = o.fno_fwd(d, x, params)
+    L_ref, gy_ref = o.mse(y_ref, target)
+    g_ref = o.fno_bwd(d, x, params, acts, gy_ref)
+    return dict(d=d, params=params, x=x, target=target, y=y_ref, acts=acts, L=L_ref, grads=g_ref)
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("dt", [torch.float32, torch.bfloat16], ids=["f32", "bf16"])
+def test_ns_network_full_size(fno, o, ns_full, dt):
+    """Forward of the whole network (every block's output and the network output) and the
+    gradient of every parameter of the training step, against the FP64 oracle at full size."""
+    print(f"ns network 64^3x16 dtype={dt}", flush=True)
+    tol = F32_TOL if dt == torch.float32 else BF16_TOL
+    params = ns_full["params"]
+    net = fno.FNO4d(4, NS_WIDTH, NS_GRID, NS_MODES, nblocks=4, dtype=dt, params=params)
+    errs = {}
+    # per-block forward outputs (Alg. 1: lifting, then each block)
+    with torch.no_grad():
+        h = fno.LiftFn.apply(dev(ns_full["x"], dt), *net.lift)
+        errs["lift_out"] = rel(np64(h), ns_full["acts"][0])
+        for bi, (w, wpw, bpw) in enumerate(net.blocks):
+            h = fno.FNOBlockFn.apply(h, w, wpw, bpw, net.plan)
+            errs[f"block{bi}_out"] = rel(np64(h), ns_full["acts"][bi + 1])
+        del h
+    y, loss, grads = run_net(fno, params, ns_full["x"], ns_full["target"], NS_GRID, NS_MODES, dt, NS_WIDTH)
+    g_ref = ns_full["grads"]
+    errs["y"] = rel(np64(y), ns_full["y"])
+    errs["loss"] = abs(loss - ns_full["L"]) / abs(ns_full["L"])
+    for k, (a, r) in enumerate(zip(grads["lift"], g_ref["lift"])):
+        errs[f"lift{k}"] = rel(np64(a), r)
+    for bi, (gb, rb) in enumerate(zip(grads["blocks"], g_ref["blocks"])):
+        for k, (a, r) in enumerate(zip(gb, rb)):
+            errs[f"block{bi}.{k}"] = rel(np64(a), r)
+    for k, (a, r) in enumerate(zip(grads["proj"], g_ref["proj"])):
+        errs[f"proj{k}"] = rel(np64(a), r)
+    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    bad = {k: v for k, v in errs.items() if not v < tol}
+    assert not bad, bad

@@ -28,6 +28,12 @@ SHAPES = {
     "full_retention_nyquist": (1, 4, 6, (8, 6, 10, 16), (4, 3, 5, 9)),
     "long_t_plane": (1, 2, 3, (4, 6, 40, 32), (2, 3, 16, 8)),
     "ns_shape_small": (1, 20, 20, (24, 20, 16, 16), (6, 5, 4, 8)),
+    # the z,t kernel variants of the CO2-shaped block (width 20, Nt 32, Kt 8: three source K
+    # chunks per tile, two t tiles) and of the batched CO2 block (width 32, Kt 10: two
+    # (re/im, kt) tiles), and the batched block's z modes (2 mz = 40)
+    "co2_tiles_w20_t32": (1, 20, 20, (4, 4, 32, 32), (2, 2, 8, 8)),
+    "batched_tiles_w32_kt10": (2, 32, 32, (4, 4, 32, 32), (2, 2, 8, 10)),
+    "batched_modes_kz40": (1, 32, 32, (4, 3, 48, 32), (2, 1, 20, 10)),
 }
 
 

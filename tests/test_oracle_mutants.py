@@ -35,6 +35,10 @@ MUTANTS = {
                                "return 0.5 * (1.0 + erf(u / sqrt(2.0)));"),
     "bias_dropped": ("double acc = bpw ? bpw[o] : 0.0;", "double acc = 0.0;"),
     "gx_pointwise_not_transposed": ("acc += wpw[o * s.Ci + i] * z[", "acc += wpw[(i % s.Co) * s.Ci + (o % s.Ci)] * z["),
+    "dft_modes_axes_swapped": ("k[a] = freq_of(&s, a, kidx[i * 4 + a]);", "k[a] = freq_of(&s, a, kidx[i * 4 + (a ^ 1)]);"),
+    "dft_modes_sign": ("th += angle(k[a], nn[a], s.N[a]);\n                double v = in[(size_t)bc * s.ncell + n];\n                re += v * cos(th);\n                im -= v * sin(th);\n            }\n            out[((size_t)bc * nk",
+                       "th += angle(k[a], nn[a], s.N[a]);\n                double v = in[(size_t)bc * s.ncell + n];\n                re += v * cos(th);\n                im += v * sin(th);\n            }\n            out[((size_t)bc * nk"),
+    "lift_gx_sign": ("acc += we[o * Ci + i] * gz[", "acc -= we[o * Ci + i] * gz["),
 }
 
 PIN_CALLS = [
@@ -49,6 +53,9 @@ PIN_CALLS = [
     lambda o: pins.test_p10_gelu(o),
     lambda o: pins.test_p11_finite_differences(o, (2, 3, 2, (6, 5, 4, 6), (2, 2, 1, 3))),
     lambda o: pins.test_p12_torch_autograd_gradient(o, (2, 3, 2, (6, 5, 4, 6), (2, 2, 1, 3))),
+    lambda o: pins.test_dft_modes_at_listed_modes(o, pins.TINY[2]),
+    lambda o: pins.test_dft_modes_impulse_closed_form(o),
+    lambda o: pins.test_lift_bwd_all_gradients_vs_torch(o),
 ]
 
 

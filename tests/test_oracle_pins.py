@@ -356,3 +356,65 @@ def test_dims_validation(oracle):
     assert not oracle.check_dims(oracle.Dims(1, 1, 1, (4, 4, 4, 4), (3, 2, 2, 3)))   # 2m > N
     assert not oracle.check_dims(oracle.Dims(1, 1, 1, (4, 4, 4, 4), (2, 2, 2, 4)))   # mt > Nt/2+1
     assert not oracle.check_dims(oracle.Dims(0, 1, 1, (4, 4, 4, 4), (1, 1, 1, 1)))
+
+
+# ---------------------------------------------------------------- sampled-mode DFT
+@pytest.mark.parametrize("spec", TINY + [(1, 2, 2, (7, 9, 5, 11), (3, 2, 2, 6))])
+def test_dft_modes_at_listed_modes(oracle, spec):
+    """oracle.dft_modes (a direct 4-D sum per listed compact index, the checker of
+    sampled outputs at full size) equals the library FFT gathered at the same
+    retained frequencies (reading S1), at every compact index -- the negative-
+    frequency corners included -- listed in a shuffled order with repeats."""
+    d = make(oracle, spec)
+    rng = np.random.default_rng(13)
+    x = rng.standard_normal((d.B, d.Ci, *d.grid))
+    ref = gather_K(np.fft.rfftn(x, axes=(2, 3, 4, 5)), d)          # [B, C, *kshape]
+    allk = np.stack(np.meshgrid(*[np.arange(k) for k in d.kshape], indexing="ij"), -1).reshape(-1, 4)
+    order = rng.permutation(len(allk))
+    kidx = np.concatenate([allk[order], allk[order[:5]]])         # shuffled, with repeated entries
+    got = oracle.dft_modes(d, x, kidx)                              # [B, C, n]
+    want = ref[:, :, kidx[:, 0], kidx[:, 1], kidx[:, 2], kidx[:, 3]]
+    assert rel(got, want) < 1e-13
+    # the corners where every spatial index is the most negative retained frequency
+    corner = np.array([[d.kshape[0] - 1, d.kshape[1] - 1, d.kshape[2] - 1, d.kshape[3] - 1],
+                       [d.modes[0], d.modes[1], d.modes[2], 0]], dtype=np.int32)
+    assert rel(oracle.dft_modes(d, x, corner), ref[:, :, corner[:, 0], corner[:, 1], corner[:, 2], corner[:, 3]]) < 1e-13
+
+
+def test_dft_modes_impulse_closed_form(oracle):
+    """x = delta(n - n0): every listed mode is exp(-i theta(k, n0)) exactly."""
+    d = oracle.Dims(1, 1, 1, (6, 5, 8, 7), (3, 2, 4, 4))
+    n0 = (5, 3, 1, 6)
+    x = np.zeros((1, 1, *d.grid))
+    x[(0, 0) + n0] = 1.0
+    kidx = np.array([[0, 0, 0, 0], [5, 3, 7, 3], [3, 2, 4, 1], [1, 1, 6, 2]], dtype=np.int32)
+    got = oracle.dft_modes(d, x, kidx)[0, 0]
+    for i, j in enumerate(kidx):
+        k = [kset(d.grid[a], d.modes[a])[j[a]] for a in range(3)] + [int(j[3])]
+        th = sum(2 * math.pi * ((k[a] * n0[a]) % d.grid[a]) / d.grid[a] for a in range(4))
+        assert abs(got[i] - complex(math.cos(th), -math.sin(th))) < 1e-14
+
+
+# ---------------------------------------------------------------- encoder input gradient
+def test_lift_bwd_all_gradients_vs_torch(oracle):
+    """Encoder backward (input, weight and bias gradients) against torch float64
+    autograd of GELU(we x + be) with the erf GELU."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(17)
+    B, Ci, Co, grid = 2, 3, 5, (4, 3, 5, 2)
+    x = rng.standard_normal((B, Ci, *grid))
+    we = rng.standard_normal((Co, Ci))
+    be = rng.standard_normal(Co)
+    gy = rng.standard_normal((B, Co, *grid))
+    gx, gwe, gbe = oracle.lift_bwd(x, we, be, gy, need_gx=True)
+    tx, tw, tb = (torch.tensor(a, requires_grad=True) for a in (x, we, be))
+    z = torch.einsum("oi,bixyzt->boxyzt", tw, tx) + tb[None, :, None, None, None, None]
+    torch.nn.functional.gelu(z).backward(torch.tensor(gy))
+    assert rel(gx, tx.grad.numpy()) < 1e-13
+    assert rel(gwe, tw.grad.numpy()) < 1e-13
+    assert rel(gbe, tb.grad.numpy()) < 1e-13
+    # without a bias the input gradient is that of GELU(we x)
+    gx0, _, _ = oracle.lift_bwd(x, we, None, gy, need_gx=True)
+    tx0 = torch.tensor(x, requires_grad=True)
+    torch.nn.functional.gelu(torch.einsum("oi,bixyzt->boxyzt", torch.tensor(we), tx0)).backward(torch.tensor(gy))
+    assert rel(gx0, tx0.grad.numpy()) < 1e-13
