@@ -26,14 +26,21 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source into libfno_mi355x.so (always rebuilds)."""
+def build(verbose: bool = False, only_changed: bool = False) -> str:
+    """Compile every source into libfno_mi355x.so (rebuilds everything unless only_changed, which
+    recompiles a source only when it or a header is newer than its object)."""
     objs = []
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
     procs = []
+    headers = glob.glob(os.path.join(HERE, "csrc", "*.h")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+    newest_header = max(os.path.getmtime(h) for h in headers)
     for src in sources():
         obj = os.path.join(build_dir, os.path.basename(src) + ".o")
+        if only_changed and os.path.exists(obj) and \
+                os.path.getmtime(obj) > max(os.path.getmtime(src), newest_header):
+            objs.append(obj)
+            continue
         cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], "-c", src, "-o", obj,
                "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -56,4 +63,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, only_changed="--changed" in sys.argv))

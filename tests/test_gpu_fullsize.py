@@ -4,7 +4,7 @@ times (same plans, same kernels):
 * the CO2-shaped block (128^3 x 32, width 20, modes 16,16,16,8, the benchmark
   workload) fwd + bwd in FP32 and BF16 against the full FP64 oracle, run once
   for both: relative L2 of y, gx, gw, gw_pw and gb (1e-5 / 1e-2) and a
-  per-element bound max|a - ref| <= c RMS(ref), which a single wrong
+  per-element bound |a - ref| <= c (|ref| + RMS(ref)), which a single wrong
   (b, c, x, y) plane (about 1/128 of the norm of one channel) would break;
 * the Navier-Stokes-shaped block (64^3 x 16, width 20, modes 12,12,12,8)
   fwd + bwd against the full FP64 oracle (every output element);
@@ -131,23 +131,26 @@ def co2_ref(o):
 
 
 def errors(dev_t, ref):
-    """(relative L2, max|a - ref| / RMS(ref)) of a device tensor against an FP64 array, one
-    leading slice at a time (host memory stays at one channel's worth of float64)."""
-    num = den = 0.0
-    amax = 0.0
+    """(relative L2, max |a - ref| / (|ref| + RMS(ref))) of a device tensor against an FP64
+    array, one leading slice at a time (host memory stays at one channel's worth of float64).
+    The per-element bound is relative where |ref| is large and absolute (in units of the RMS)
+    where it is small: a wrong (b, c, x, y) plane of an activation gives about 0.5 whatever the
+    norm, and a heavy-tailed spectral gradient is held to its own precision at every entry."""
     t = dev_t.detach()
     lead = t.shape[0] * t.shape[1] if t.dim() >= 3 else 1
     tv = t.reshape(lead, -1)
     rv = np.asarray(ref).reshape(lead, -1)
+    den = float(sum(np.sum(np.abs(rv[i]) ** 2) for i in range(lead)))
+    rms = np.sqrt(den / rv.size)
+    num = 0.0
+    worst = 0.0
     for i in range(lead):
         a = tv[i].cpu()
         a = a.numpy().astype(np.complex128) if a.is_complex() else a.float().numpy().astype(np.float64)
         diff = np.abs(a - rv[i])
         num += float(np.sum(diff ** 2))
-        den += float(np.sum(np.abs(rv[i]) ** 2))
-        amax = max(amax, float(diff.max()))
-    rms = np.sqrt(den / rv.size)
-    return np.sqrt(num / den), amax / rms
+        worst = max(worst, float(np.max(diff / (np.abs(rv[i]) + rms))))
+    return np.sqrt(num / den), worst
 
 
 @pytest.mark.timeout(1200)
@@ -165,7 +168,7 @@ def test_co2_block_full_size(fno, o, co2_ref, code, tol, cmax):
     torch.cuda.synchronize()
     got = dict(y=y, gx=gx, gw=gw, gw_pw=gwpw, gb=gb)
     res = {k: errors(got[k], co2_ref["ref"][k]) for k in got}
-    print({k: f"rel {v[0]:.2e} max/rms {v[1]:.2e}" for k, v in res.items()}, flush=True)
+    print({k: f"rel {v[0]:.2e} elem {v[1]:.2e}" for k, v in res.items()}, flush=True)
     for k, (e, m) in res.items():
         assert e < tol, (k, e)
         assert m < cmax, (k, m)
