@@ -118,6 +118,21 @@ int fno_spectral_bwd(const fno_plan_t *plan, const void *x, const void *cache, c
                      const void *gy, void *gx, void *gw, int accumulate,
                      void *ws, size_t ws_bytes, void *stream);
 
+/* Allocation-free variant of fno_spectral_fwd, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same operation, arguments and layouts as
+ * fno_spectral_fwd, without the workspace: the intermediates live in a static
+ * device array of FNO_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * GPU it runs on until the process ends.  Returns FNO_ERR_WORKSPACE, before
+ * anything is launched, when the plan's spectral-forward workspace
+ * (fno_workspace_bytes(plan, FNO_OP_SPECTRAL_FWD)) exceeds that size.  The
+ * array needs no clearing between calls (every call writes each intermediate
+ * before reading it).  All calls on one GPU share the array: calls that
+ * overlap on one GPU (other streams, other host threads) race and must be
+ * serialised by the caller.  Calls no allocating routine. */
+#define FNO_NOALLOC_SCRATCH_BYTES (32u << 20)
+int fno_spectral_fwd_noalloc(const fno_plan_t *plan, const void *x, const void *w, void *y, void *cache, void *stream);
+
 /* FNO block (Alg. 1, block line): y = GELU(S(x; w) + w_pw x + b_pw).
  * b_pw may be NULL (no bias).  cache (nullable) receives what fno_block_bwd
  * needs to recompute the pre-activation (the full-size pre-activation itself

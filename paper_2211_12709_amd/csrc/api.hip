@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -613,6 +614,45 @@ int fno_spectral_bwd(const fno_plan_t *plan, const void *x, const void *cache, c
     if (plan->desc.dtype == FNO_BF16)
         return spectral_bwd_impl<__bf16>(plan, x, cache, w, gy, gx, gw, accumulate, ws, ws_bytes, stream);
     return spectral_bwd_impl<float>(plan, x, cache, w, gy, gx, gw, accumulate, ws, ws_bytes, stream);
+}
+
+// ---- the allocation-free variant of fno_spectral_fwd
+// Its workspace is a file-scope device array.  In host code the array's name is only a stand-in
+// for the symbol: its device address comes from hipGetSymbolAddress, taken once per device (that
+// GPU's own copy) and kept in g_scratch_ptr; only that pointer is ever handed to a kernel.
+static __device__ __align__(256) char scratch[FNO_NOALLOC_SCRATCH_BYTES];
+static const int kMaxDevices = 64;
+static void *g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+static int scratch_ptr(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return FNO_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return FNO_ERR_HIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FNO_OK;
+}
+
+int fno_spectral_fwd_noalloc(const fno_plan_t *plan, const void *x, const void *w, void *y, void *cache, void *stream)
+{
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    const size_t need = ws_plan(plan->d, FNO_OP_SPECTRAL_FWD).total;
+    if (need > (size_t)FNO_NOALLOC_SCRATCH_BYTES) return FNO_ERR_WORKSPACE;
+    void *ws = nullptr;
+    rc = scratch_ptr(plan->device, &ws);
+    if (rc) return rc;
+    if (plan->desc.dtype == FNO_BF16)
+        return spectral_or_block_fwd<__bf16>(plan, x, w, nullptr, nullptr, y, cache, ws, need, stream, false);
+    return spectral_or_block_fwd<float>(plan, x, w, nullptr, nullptr, y, cache, ws, need, stream, false);
 }
 
 int fno_block_fwd(const fno_plan_t *plan, const void *x, const void *w, const void *w_pw, const void *b_pw, void *y,

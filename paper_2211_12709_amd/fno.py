@@ -24,9 +24,10 @@ FNO_F32, FNO_BF16 = 0, 1
 OP_SPECTRAL_FWD, OP_SPECTRAL_BWD, OP_BLOCK_FWD, OP_BLOCK_BWD = range(4)
 
 EXPORTS = ("fno_desc_validate", "fno_plan_create", "fno_plan_destroy", "fno_workspace_bytes", "fno_cache_bytes",
-           "fno_spectral_fwd", "fno_spectral_bwd", "fno_block_fwd", "fno_block_bwd", "fno_lift_fwd", "fno_lift_bwd",
-           "fno_proj_fwd", "fno_proj_bwd", "fno_mse", "fno_glue_workspace_bytes", "fno_timing_enable",
-           "fno_timing_read", "fno_status_str")
+           "fno_spectral_fwd", "fno_spectral_fwd_noalloc", "fno_spectral_bwd", "fno_block_fwd", "fno_block_bwd",
+           "fno_lift_fwd", "fno_lift_bwd", "fno_proj_fwd", "fno_proj_bwd", "fno_mse", "fno_glue_workspace_bytes",
+           "fno_timing_enable", "fno_timing_read", "fno_status_str")
+NOALLOC_SCRATCH_BYTES = 32 << 20  # FNO_NOALLOC_SCRATCH_BYTES
 
 
 class Desc(ctypes.Structure):
@@ -60,6 +61,7 @@ def load_library(path: str = LIB_PATH):
     L.fno_workspace_bytes.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(_sz)]
     L.fno_cache_bytes.argtypes = [_vp, ctypes.POINTER(_sz)]
     L.fno_spectral_fwd.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
+    L.fno_spectral_fwd_noalloc.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
     L.fno_spectral_bwd.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _sz, _vp]
     L.fno_block_fwd.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]
     L.fno_block_bwd.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp, _sz, _vp]
@@ -184,6 +186,13 @@ class Plan:
         ws = self.workspace(OP_SPECTRAL_FWD)
         _check(_lib.fno_spectral_fwd(self._h, _ptr(x), _ptr(w), _ptr(y), _ptr(cache), _ptr(ws), ws.numel(),
                                      _stream()), "fno_spectral_fwd")
+        return y
+
+    def spectral_fwd_noalloc(self, x, w, y, cache=None):
+        """fno_spectral_fwd_noalloc: the forward without a workspace (the library's static device
+        array holds the intermediates); y (and cache) are caller-allocated."""
+        _check(_lib.fno_spectral_fwd_noalloc(self._h, _ptr(x), _ptr(w), _ptr(y), _ptr(cache), _stream()),
+               "fno_spectral_fwd_noalloc")
         return y
 
     def spectral_bwd(self, gy, w, x=None, cache=None, gx=None, gw=None, need_gx=True, need_gw=True, accumulate=False):
