@@ -44,11 +44,15 @@ struct TzyTabs {
     const void *t, *t_lo, *z, *z_lo, *y, *y_lo;
 };
 bool tzy_supported(const Dims &d, int dtype);
+bool tzy_gen_supported(const Dims &d, int dtype);
+template <typename T>
+hipError_t launch_tzy_gen(const T *x, float2 *t2, long long slabs, const TzyTabs &tb, const Dims &d, hipStream_t st);
 struct ZtTabs {
     const void *z, *z_lo, *t, *t_lo;
 };
 enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3 };
 bool zt_supported(const Dims &d, int dtype);
+bool zt_t_sliced(const Dims &d);
 int zt_grid(const Dims &d);
 template <typename T>
 hipError_t launch_zt(int epi, const Dims &d, int Cs, int Csrc, const void *u, T *out, const T *src, const T *gy,
@@ -254,9 +258,13 @@ static void forward_spectrum(const fno_plan_t *p, const T *in, int C, const floa
                              float2 *xh, hipStream_t st)
 {
     const Dims &d = p->d;
-    if (tzy_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
+    const int dt = sizeof(T) == 2 ? FNO_BF16 : FNO_F32;
+    if (tzy_supported(d, dt)) {
         FNO_TIMED(p, st, sizeof(T) == 2 ? "tzy_fwd<bf16>" : "tzy_fwd<f32>",
                   note(launch_tzy<T>(in, t2, (long long)d.B * C * d.N[0], tzy_tabs<T>(p, wt), d, st)));
+    } else if (tzy_gen_supported(d, dt)) {
+        FNO_TIMED(p, st, sizeof(T) == 2 ? "tzy_gen<bf16>" : "tzy_gen<f32>",
+                  note(launch_tzy_gen<T>(in, t2, (long long)d.B * C * d.N[0], tzy_tabs<T>(p, wt), d, st)));
     } else {
         FNO_TIMED(p, st, sizeof(T) == 2 ? "fwd_tz<bf16>" : "fwd_tz<f32>",
                   launch_fwd_tz<T>(in, t1, (long long)d.B * C * d.N[0] * d.N[1], d, p->tab, wt, st));
@@ -308,7 +316,8 @@ static int spectral_or_block_fwd(const fno_plan_t *p, const void *x_, const void
     FNO_TIMED(p, st, "mix_fwd", launch_mix_fwd(xh, (const float2 *)w_, yh, d.B, d.Ci, d.Co, d.nmode, st));
     inverse_xy(p, yh, d.Co, u2, t1, st);
     if (zt_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
-        FNO_TIMED(p, st, block ? "zt_block" : "zt_plain",
+        const bool gen = zt_t_sliced(d);
+        FNO_TIMED(p, st, block ? (gen ? "zt_block_tsl" : "zt_block") : (gen ? "zt_plain_tsl" : "zt_plain"),
                   note(launch_zt<T>(block ? ZEPI_BLOCK : ZEPI_PLAIN, d, d.Co, block ? d.Ci : 0, t1, (T *)y_, x,
                                      nullptr, (const float *)wpw, (const float *)bpw, nullptr, zt_tabs<T>(p, false), 0,
                                      st)));
@@ -354,7 +363,7 @@ static int spectral_bwd_impl(const fno_plan_t *p, const void *x_, const void *ca
     if (gx_) {
         inverse_xy(p, gxh, d.Ci, t2, t1, st);
         if (zt_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
-            FNO_TIMED(p, st, "zt_adj",
+            FNO_TIMED(p, st, zt_t_sliced(d) ? "zt_adj_tsl" : "zt_adj",
                       note(launch_zt<T>(ZEPI_ADJ, d, d.Ci, 0, t1, (T *)gx_, nullptr, nullptr, nullptr, nullptr,
                                          nullptr, zt_tabs<T>(p, true), accumulate, st)));
         } else {
@@ -393,7 +402,8 @@ static int block_bwd_impl(const fno_plan_t *p, const void *x_, const void *cache
     if (zt_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
         T *gzt = (T *)gz;  // gz stored in the activation type
         int rows_used = zt_partial_rows(d);
-        FNO_TIMED(p, st, "zt_bwd",
+        const bool gen = zt_t_sliced(d);
+        FNO_TIMED(p, st, gen ? "zt_bwd_tsl" : "zt_bwd",
                   note(launch_zt<T>(ZEPI_BWD, d, d.Co, d.Ci, t1, gzt, x, (const T *)gy_, wpw, bpw, part,
                                      zt_tabs<T>(p, false), 0, st, &rows_used)));
         if (gwpw_ || gb_)
@@ -404,7 +414,7 @@ static int block_bwd_impl(const fno_plan_t *p, const void *x_, const void *cache
                   launch_mix_bwd(xh, (const float2 *)w_, gyh, gxh, (float2 *)gw_, d.B, d.Ci, d.Co, d.nmode, accumulate,
                                  st));
         inverse_xy(p, gxh, d.Ci, t2, t1, st);
-        FNO_TIMED(p, st, "zt_adj",
+        FNO_TIMED(p, st, gen ? "zt_adj_tsl" : "zt_adj",
                   note(launch_zt<T>(ZEPI_ADJ, d, d.Ci, d.Co, t1, (T *)gx_, gzt, nullptr, wpw, nullptr, nullptr,
                                      zt_tabs<T>(p, true), accumulate, st)));
         return finish();

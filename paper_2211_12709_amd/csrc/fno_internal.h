@@ -47,6 +47,14 @@ struct Dims {
     long long P;          // Ky Kz Kt
 };
 
+// Geometry of the forward t, z, y kernels (fwd_tzy.hip, fwd_tzy_gen.hip): y, z, t sizes and retained
+// counts; t chunks of 16, z blocks of 16, kz blocks of 16 and z-step row tiles (cos, sin), y-step
+// row tiles (re, im), y planes per staged chunk, its K chunks, and the chunk count.
+struct TzyArgs {
+    int Ny, Nz, Nt, Ky, Kz, Kt;
+    int NQ, NZB, KB, MZ, MY, Yc, QY, NYC;
+};
+
 }  // namespace fno
 
 namespace fno {
@@ -132,6 +140,35 @@ __device__ __forceinline__ float gelu_grad_fast(float u)
     float q, e;
     gelu_tail(u, q, e);
     return fmaf(u * 0.39894228040143268f, e, u >= 0.0f ? 1.0f - q : q);
+}
+
+// Cheaper forms for the bfloat16 epilogues, whose results are rounded to bfloat16 (relative step
+// 2^-8): Phi by the logistic approximation of Bowling, Khasawneh, Kaewkuekool and Cho (2009), "A
+// logistic approximation to the cumulative normal distribution",
+//   Phi(u) ~ 1 / (1 + exp(-(1.5976 u + 0.07056 u^3))),  |error| <= 1.4e-4,
+// so GELU(u) = u Phi(u) is within 1.1e-4 (|u| + 1) and GELU'(u) = Phi(u) + u phi(u) (phi exact)
+// within 1.4e-4; 7 and 10 instructions per value against 14 and 18 above.  The constants below
+// carry the factor log2(e) of the base-2 exponential.
+__device__ __forceinline__ float phi_logistic(float u, float u2)
+{
+    const float a = u * fmaf(u2, -0.10179656f, -2.30484960f);  // -(1.5976 u + 0.07056 u^3) log2(e)
+    return __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(a));
+}
+__device__ __forceinline__ float gelu_lg(float u) { return u * phi_logistic(u, u * u); }
+__device__ __forceinline__ float gelu_grad_lg(float u)
+{
+    const float u2 = u * u;
+    const float e = __builtin_amdgcn_exp2f(u2 * -0.72134752044448170f);  // exp(-u^2 / 2)
+    return fmaf(u * 0.39894228040143268f, e, phi_logistic(u, u2));
+}
+// The derivative of u P(u) with P the logistic approximation itself, P' = P (1 - P) g'(u),
+// g(u) = 1.5976 u + 0.07056 u^3: within 7.9e-4 of the exact GELU', one exponential fewer.
+__device__ __forceinline__ float gelu_grad_lgd(float u)
+{
+    const float u2 = u * u;
+    const float P = phi_logistic(u, u2);
+    const float gp = fmaf(u2, 0.21168f, 1.5976f);
+    return fmaf(u * fmaf(-P, P, P), gp, P);
 }
 
 }  // namespace fno

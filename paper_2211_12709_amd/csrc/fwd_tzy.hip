@@ -36,10 +36,6 @@ template <typename T> constexpr int tzy_nw() { return sizeof(T) == 2 ? FNO_TZY_N
 
 namespace fno {
 
-struct TzyArgs {
-    int Ny, Nz, Nt, Ky, Kz, Kt;
-    int NQ, NZB, KB, MZ, MY, Yc, QY, NYC;
-};
 
 // NTT: N tiles of the t/z steps (1: Kt <= 8, re|im in one tile; 2: Kt <= 16).
 // MY: row tiles of the y step (2 ceil(Ky/16)); NBW: its column tiles per wave.

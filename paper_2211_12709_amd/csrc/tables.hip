@@ -93,12 +93,13 @@ __global__ void k_gen_tab(int kind, TabGeom G, long long n, float *__restrict__ 
             v = ri == 0 ? cos(th) : sin(th);
         }
     } else if (kind == TAB_TI_INV || kind == TAB_TI_ADJ) {
-        // A[t][(ri, kt)] for t tile mt and K chunk q: w cos (ri = 0) / -w sin (ri = 1) of 2 pi kt t / Nt.
-        // Row c of tile mt is t = 4 NTQ (c / 4) + 4 mt + c % 4 (NTQ = t tiles), so that an output lane
-        // 16 g' + c' holds the 4 NTQ consecutive t = 4 NTQ g' .. of column c' across the tiles.
-        const int q = (int)(tile % G.NTT), mt = (int)(tile / G.NTT);
-        const int ntq = (G.Nt + 15) / 16;
-        const int t = 4 * ntq * (c >> 2) + 4 * mt + (c & 3), k = 16 * q + 4 * g + j;
+        // A[t][(ri, kt)] for t tile mt of t slice ts and K chunk q: w cos (ri = 0) / -w sin (ri = 1) of
+        // 2 pi kt t / Nt.  A slice is NTQ t tiles (NTQ = 1 for Nt <= 16, else 2: 32 t); row c of tile mt
+        // of slice ts is t = 16 NTQ ts + 4 NTQ (c / 4) + 4 mt + c % 4, so that an output lane 16 g' + c'
+        // holds the 4 NTQ consecutive t = 16 NTQ ts + 4 NTQ g' .. of column c' across the slice's tiles.
+        const int q = (int)(tile % G.NTT), st = (int)(tile / G.NTT);
+        const int ntq = G.Nt > 16 ? 2 : 1, ts = st / ntq, mt = st % ntq;
+        const int t = 16 * ntq * ts + 4 * ntq * (c >> 2) + 4 * mt + (c & 3), k = 16 * q + 4 * g + j;
         const int ri = G.NTT == 1 ? k / 8 : q;
         const int kt = G.NTT == 1 ? k % 8 : k - 16 * q;
         if (t < G.Nt && kt < G.Kt) {
@@ -162,7 +163,10 @@ long long tab_values(int kind, const TabGeom &G)
     case TAB_Y_FWD: return (long long)G.NYC * G.QY * G.MY * 256;
     case TAB_ZI: return (long long)G.NZB * (2 * G.Kzp / 16) * 256;
     case TAB_TI_INV:
-    case TAB_TI_ADJ: return (long long)((G.Nt + 15) / 16) * G.NTT * 256;
+    case TAB_TI_ADJ: {
+        const int ntq = G.Nt > 16 ? 2 : 1;  // t tiles per slice; slices cover Nt
+        return (long long)((G.Nt + 16 * ntq - 1) / (16 * ntq)) * ntq * G.NTT * 256;
+    }
     case TAB_AXF:
     case TAB_AXI: return (long long)(2 * G.axNoutp / 16) * (2 * G.axNinp / 16) * 256;
     }

@@ -34,6 +34,42 @@ SHAPES = {
     "co2_tiles_w20_t32": (1, 20, 20, (4, 4, 32, 32), (2, 2, 8, 8)),
     "batched_tiles_w32_kt10": (2, 32, 32, (4, 4, 32, 32), (2, 2, 8, 10)),
     "batched_modes_kz40": (1, 32, 32, (4, 3, 48, 32), (2, 1, 20, 10)),
+    # the batched CO2 block's y and z modes together (2 my = 2 mz = 40, 10 t bins): the general
+    # forward t,z,y kernel (three kz blocks, six y-step row tiles)
+    "batched_modes_ky40_kz40": (1, 32, 32, (4, 40, 48, 32), (2, 20, 20, 10)),
+    # reduced copies of the paper's own grids (Sec. V): Navier-Stokes 130^3 x 64 (Nz 130, Nt 64,
+    # two t slices) and CO2 262 x 118 x 64 x 86 (Nt 86: rows not 4-aligned), about 20% of the
+    # frequencies kept per axis, at small and at full width
+    "ns_true_z130_t64": (1, 3, 4, (4, 3, 130, 64), (2, 1, 13, 7)),
+    "ns_true_w20": (1, 20, 20, (3, 3, 40, 64), (1, 1, 8, 7)),
+    "co2_true_t86": (1, 4, 4, (10, 6, 64, 86), (5, 3, 6, 9)),
+    "co2_true_w20": (1, 20, 20, (4, 4, 64, 86), (2, 2, 6, 9)),
+    # odd Nt beyond one t slice (element-wise rows), and more t bins than the matrix-core
+    # kernels take (the scalar kernels)
+    "odd_t45": (1, 3, 5, (4, 5, 20, 45), (2, 2, 5, 12)),
+    "scalar_kt21": (1, 2, 3, (4, 4, 6, 40), (2, 2, 3, 21)),
+}
+
+# the kernels each shape must run on: forward t,z,y (k_tzy_fwd "tzy_fwd", the general
+# "tzy_gen", or the scalar "fwd_tz") and z,t epilogue (matrix-core "zt_*", t-sliced "zt_*_tsl",
+# or the scalar "inv_zt_*"; a pair (float, bfloat16) where the dtypes differ: at width 32 with
+# 2 mz = 40 the float epilogue's U tile alone needs more LDS than a workgroup has)
+PATHS = {
+    "single_layer_16^3x8": ("tzy_fwd", "zt_block"),
+    "odd_ragged": ("tzy_gen", "zt_block_tsl"),
+    "full_retention_nyquist": ("tzy_fwd", "zt_block"),
+    "long_t_plane": ("tzy_fwd", "zt_block"),
+    "ns_shape_small": ("tzy_fwd", "zt_block"),
+    "co2_tiles_w20_t32": ("tzy_fwd", "zt_block"),
+    "batched_tiles_w32_kt10": ("tzy_fwd", "zt_block"),
+    "batched_modes_kz40": ("tzy_gen", ("inv_zt_block", "zt_block")),
+    "batched_modes_ky40_kz40": ("tzy_gen", ("inv_zt_block", "zt_block")),
+    "ns_true_z130_t64": ("tzy_gen", "zt_block_tsl"),
+    "ns_true_w20": ("tzy_gen", "zt_block_tsl"),
+    "co2_true_t86": ("tzy_gen", "zt_block_tsl"),
+    "co2_true_w20": ("tzy_gen", "zt_block_tsl"),
+    "odd_t45": ("tzy_gen", "zt_block_tsl"),
+    "scalar_kt21": ("fwd_tz", "inv_zt_block"),
 }
 
 
@@ -152,6 +188,27 @@ def test_block_fwd_bwd(fno, o, name, dt):
     say("  rel " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     for k, v in errs.items():
         assert v < tol(dt), (k, v)
+
+
+@pytest.mark.parametrize("name", sorted(SHAPES))
+def test_kernel_paths(fno, name):
+    """Each shape runs on the kernels it is meant to exercise (names from the per-kernel timing)."""
+    B, Ci, Co, grid, modes = SHAPES[name]
+    want_fwd, want_epi = PATHS[name]
+    for dt in (0, 1):
+        plan = fno.Plan(B, Ci, Co, grid, modes, dt)
+        x = torch.zeros((B, Ci, *grid), dtype=plan.act_dtype, device="cuda")
+        w = torch.zeros((Ci, Co, *plan.kshape), dtype=torch.complex64, device="cuda")
+        wpw = torch.zeros((Co, Ci), device="cuda")
+        plan.timing(True)
+        plan.block_fwd(x, w, wpw)
+        names = set(plan.timing_read())
+        plan.timing(False)
+        say(f"{name} dtype={dt}: {sorted(names)}")
+        fwd = {n.split("<")[0] for n in names} & {"tzy_fwd", "tzy_gen", "fwd_tz"}
+        assert fwd == {want_fwd}, (name, dt, names)
+        epi = want_epi if isinstance(want_epi, str) else want_epi[dt]
+        assert epi in names, (name, dt, names)
 
 
 def test_block_without_bias_and_accumulate(fno, o):
