@@ -41,7 +41,14 @@ WORKLOADS = {
     "ns_block_64^3x16": (1, 20, (64, 64, 64, 16), (12, 12, 12, 8)),
     "co2_batched_block_128^3x32": (4, 32, (128, 128, 128, 32), (20, 20, 20, 10)),
     "single_layer_16^3x8": (1, 8, (16, 16, 16, 8), (4, 4, 4, 4)),
+    # the paper's own grids (Sec. V-A: Navier-Stokes 130^3 x 64; Sec. V-B: CO2 262 x 118 x 64 x 86)
+    # at width 20, keeping about 20% of the frequencies per axis (2 m ~ N / 5, 2 mt - 1 ~ Nt / 5)
+    "ns_true_130^3x64": (1, 20, (130, 130, 130, 64), (13, 13, 13, 7)),
+    "co2_true_262x118x64x86": (1, 20, (262, 118, 64, 86), (26, 12, 6, 9)),
 }
+# timed beside the headline in a default run (BF16 only, device-generated inputs, no oracle: their
+# parity is tested at reduced grids that run the same kernel variants)
+EXTRA_WORKLOADS = ("ns_true_130^3x64", "co2_true_262x118x64x86", "co2_batched_block_128^3x32")
 
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
@@ -102,6 +109,8 @@ def kernel_model(name, B, Ci, Co, grid, modes, act_bytes):
     models = {
         "tzy_fwd<bf16>": (B * C * N * 2 + t2, t_fl + z_fl + y_fl),
         "tzy_fwd<f32>": (B * C * N * 4 + t2, t_fl + z_fl + y_fl),
+        "tzy_gen<bf16>": (B * C * N * 2 + t2, t_fl + z_fl + y_fl),
+        "tzy_gen<f32>": (B * C * N * 4 + t2, t_fl + z_fl + y_fl),
         "zt_plain": (u1 + A, t_fl + z_fl),
         "zt_block": (u1 + 2 * A, t_fl + z_fl + pw),
         "zt_bwd": (u1 + 3 * A, t_fl + z_fl + 2 * pw),
@@ -113,6 +122,7 @@ def kernel_model(name, B, Ci, Co, grid, modes, act_bytes):
         "mix_fwd": (2 * sp + W, 8 * B * Ci * Co * kx * ky * kz * mt),
         "mix_bwd": (3 * sp + 2 * W, 16 * B * Ci * Co * kx * ky * kz * mt),
     }
+    name = name[:-4] if name.endswith("_tsl") else name  # t-sliced variants do the same work
     if name not in models:
         return None
     by, fl = models[name]
@@ -124,8 +134,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "paper_2211_12709_amd", "csrc")
 # sources whose text decides a kernel's memory traffic (a counter figure is stale once they change)
 KERNEL_SOURCES = {
-    "zt": ["zt_epi.hip", "tables.hip", "mfma_common.h", "fno_internal.h"],
-    "tzy": ["fwd_tzy.hip", "tables.hip", "mfma_common.h", "fno_internal.h"],
+    "zt": ["zt_epi.h", "zt_epi.hip", "zt_epi_block.hip", "zt_epi_bwd.hip", "zt_epi_adj.hip", "zt_epi_plain.hip",
+           "tables.hip", "mfma_common.h", "fno_internal.h"],
+    "tzy": ["fwd_tzy.hip", "fwd_tzy_gen.hip", "tables.hip", "mfma_common.h", "fno_internal.h"],
 }
 
 
@@ -188,6 +199,101 @@ def rel(a, ref):
     return float(np.linalg.norm((a - ref).ravel()) / max(np.linalg.norm(ref.ravel()), 1e-300))
 
 
+def roofline_of(kern, wl, workload):
+    """Roofline object of the dominant (longest) kernel of a BF16 step from its per-kernel timings
+    {name: (launches, total_ms)}: algorithmic bytes (or flops) of one launch over its average time."""
+    B, C, grid, modes = wl
+    name, (launches, tot_ms) = max(kern.items(), key=lambda kv: kv[1][1])
+    avg_ms = tot_ms / launches
+    km = kernel_model(name, B, C, C, grid, modes, 2)
+    if km is None:
+        return None
+    t_hbm = km["bytes"] / (HBM_PEAK_GBS * 1e9)
+    t_mfma = km["flops"] / (MFMA_PEAK_TFLOPS["bf16"] * 1e12)
+    if t_hbm >= t_mfma:
+        ach = km["bytes"] / (avg_ms * 1e-3) / 1e9
+        return dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                    traffic=profiled_traffic(name, "bf16", workload), kernel=name, avg_ms=avg_ms,
+                    bytes_per_launch=km["bytes"])
+    ach = km["flops"] / (avg_ms * 1e-3) / 1e12
+    return dict(bound="mfma", achieved=ach, peak=MFMA_PEAK_TFLOPS["bf16"], unit="TFLOP/s",
+                frac=ach / MFMA_PEAK_TFLOPS["bf16"], traffic=None, kernel=name, avg_ms=avg_ms)
+
+
+def time_steps(step, steps, warmup, kernel_steps, plan):
+    """Times `steps` back-to-back calls of step() with one event between consecutive steps, then
+    a separate pass of kernel_steps steps with every kernel launch bracketed by events."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs[0].record(stream)
+    for k in range(steps):
+        step()
+        evs[k + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_step = [evs[k].elapsed_time(evs[k + 1]) for k in range(steps)]
+    ms = evs[0].elapsed_time(evs[-1]) / steps
+    plan.timing(True)
+    plan.timing_read()
+    for _ in range(kernel_steps):
+        step()
+    torch.cuda.synchronize()
+    plan.timing(False)
+    kern = plan.timing_read()
+    med, lo, hi = median_ci(per_step)
+    return dict(ms=ms, wall_ms=wall * 1000 / steps, kernels=kern, median_ms=med, ci95_ms=[lo, hi],
+                kernel_steps=kernel_steps)
+
+
+def run_extra(name, steps, warmup):
+    """BF16 block fwd+bwd timing of another workload: inputs and weights drawn on the device (seeded
+    normal values; the kernels' work does not depend on them), no oracle."""
+    import torch
+
+    from paper_2211_12709_amd import fno, inputs
+
+    B, C, grid, modes = WORKLOADS[name]
+    dev = torch.device("cuda", 0)
+    ksh = (2 * modes[0], 2 * modes[1], 2 * modes[2], modes[3])
+    log(f"[bench] {name}: B={B} C={C} grid={grid} modes={modes}")
+    g = torch.Generator(device=dev)
+    g.manual_seed(inputs.SEED_INPUT)
+    plan = fno.Plan(B, C, C, grid, modes, fno.FNO_BF16)
+    xa = torch.randn((B, C, *grid), generator=g, device=dev, dtype=torch.bfloat16)
+    gya = torch.randn((B, C, *grid), generator=g, device=dev, dtype=torch.bfloat16)
+    tw = torch.randn((C, C, *ksh), generator=g, device=dev, dtype=torch.complex64) / C
+    twp = torch.randn((C, C), generator=g, device=dev) / C ** 0.5
+    tb = torch.zeros((C,), device=dev)
+    cache = plan.new_cache()
+    y, gx = torch.empty_like(xa), torch.empty_like(xa)
+    gw = torch.empty_like(tw)
+    gwpw = torch.empty_like(twp)
+    gb = torch.empty_like(tb)
+
+    def step():
+        plan.block_fwd(xa, tw, twp, tb, y=y, cache=cache)
+        plan.block_bwd(xa, cache, tw, twp, tb, gya, gx=gx, gw=gw, gw_pw=gwpw, gb_pw=gb)
+
+    r = time_steps(step, steps, warmup, 1, plan)
+    fm = flop_model(B, C, C, grid, modes)
+    wl = WORKLOADS[name]
+    out = dict(config={"batch": B, "width": C, "grid": list(grid), "modes": list(modes)}, dtype="bf16",
+               ms_per_step=r["ms"], median_ms_per_step=r["median_ms"], ci95_ms_per_step=r["ci95_ms"],
+               tflops=(fm["fwd"] + fm["bwd"]) / (r["ms"] * 1e-3) / 1e12,
+               kernels_ms_per_step={k: v[1] for k, v in r["kernels"].items()},
+               roofline=roofline_of(r["kernels"], wl, name), data="synthetic (device normal draws)")
+    log(f"[bench] {name}: {r['ms']:.3f} ms/step")
+    del plan, xa, gya, cache, y, gx, tw, gw
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_gpu(args, wl):
     import torch
 
@@ -233,57 +339,80 @@ def run_gpu(args, wl):
             plan.block_fwd(xa, tw, twp, tb, y=y, cache=cache)
             plan.block_bwd(xa, cache, tw, twp, tb, gya, gx=gx, gw=gw, gw_pw=gwpw, gb_pw=gb)
 
-        log(f"[bench] {dt_name}: warmup {args.warmup}")
-        for _ in range(args.warmup):
-            step()
-        torch.cuda.synchronize()
-        log(f"[bench] {dt_name}: timing {args.steps} steps")
-        # headline: the K steps back to back, one event between consecutive steps (no per-kernel events)
-        stream = torch.cuda.current_stream()
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        evs[0].record(stream)
-        for k in range(args.steps):
-            step()
-            evs[k + 1].record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        per_step = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
-        ms = evs[0].elapsed_time(evs[-1]) / args.steps
-        # per-kernel durations: a separate pass of the same steps with every launch bracketed by
-        # HIP events on its stream (the library's timing records)
-        plan.timing(True)
-        plan.timing_read()
-        for _ in range(args.kernel_steps):
-            step()
-        torch.cuda.synchronize()
-        plan.timing(False)
-        kern = plan.timing_read()
-        med, lo, hi = median_ci(per_step)
-        results[dt_name] = dict(ms=ms, wall_ms=wall * 1000 / args.steps, kernels=kern, median_ms=med,
-                                ci95_ms=[lo, hi], kernel_steps=args.kernel_steps)
+        log(f"[bench] {dt_name}: warmup {args.warmup}, timing {args.steps} steps")
+        results[dt_name] = time_steps(step, args.steps, args.warmup, args.kernel_steps, plan)
+        ms = results[dt_name]["ms"]
         log(f"[bench] {dt_name}: {ms:.3f} ms/step")
         if not args.no_oracle:
-            outputs[dt_name] = dict(y=y.float().cpu().numpy(), gx=gx.float().cpu().numpy(),
-                                    gw=gw.cpu().numpy(), gw_pw=gwpw.cpu().numpy(), gb=gb.cpu().numpy())
+            # activations stay in their own dtype on the host (compared a channel at a time)
+            outputs[dt_name] = dict(y=y.cpu(), gx=gx.cpu(), gw=gw.cpu().numpy(), gw_pw=gwpw.cpu().numpy(),
+                                    gb=gb.cpu().numpy())
         del plan, xa, gya, cache, y, gx
         torch.cuda.empty_cache()
     return results, outputs, (x, gy, w, wpw, bpw)
 
 
-def run_oracle(wl, data):
+class ErrAcc:
+    """Relative L2 error accumulated over slices: sqrt(sum |a - ref|^2 / sum |ref|^2)."""
+
+    def __init__(self):
+        self.num = self.den = 0.0
+
+    def add(self, a, ref):
+        a = np.asarray(a, dtype=np.complex128 if np.iscomplexobj(ref) else np.float64)
+        self.num += float(np.sum(np.abs(a - ref) ** 2))
+        self.den += float(np.sum(np.abs(ref) ** 2))
+
+    def value(self):
+        return float(np.sqrt(self.num / max(self.den, 1e-300)))
+
+
+def compare_acts(acc, dev_cpu, ref, b0=0):
+    """Adds to `acc` the error of a host copy of a device activation [B][C][...] (any dtype) against
+    an FP64 oracle array covering batch elements b0.. of it, one (b, c) slice at a time."""
+    for b in range(ref.shape[0]):
+        for c in range(ref.shape[1]):
+            acc.add(dev_cpu[b0 + b, c].float().numpy(), ref[b, c])
+
+
+def run_oracle(wl, data, outputs):
+    """FP64 oracle block fwd + bwd on the benchmark inputs and the relative L2 errors of every
+    output of `outputs` ({dtype: {name: host array}}).  Batch elements are run one at a time
+    (memory stays at one element's FP64 activations): output and input-gradient errors are
+    accumulated over them, and the weight gradients, sums over the batch, are summed first."""
     from oracle import oracle as o
     B, C, grid, modes = wl
     x, gy, w, wpw, bpw = data
-    d = o.Dims(B, C, C, grid, modes)
-    log("[bench] oracle (FP64 CPU) block fwd+bwd")
-    t0 = time.perf_counter()
-    y = o.block_fwd(d, x, w, wpw, bpw)
-    gx, gw, gwpw, gb = o.block_bwd(d, x, w, wpw, bpw, gy)
-    sec = time.perf_counter() - t0
+    d1 = o.Dims(1, C, C, grid, modes)
+    log("[bench] oracle (FP64 CPU) block fwd+bwd" + (f", streamed over {B} batch elements" if B > 1 else ""))
+    acc = {dt: dict(y=ErrAcc(), gx=ErrAcc()) for dt in outputs}
+    sums = None
+    sec = 0.0
+    for b in range(B):
+        t0 = time.perf_counter()
+        y = o.block_fwd(d1, x[b:b + 1], w, wpw, bpw)
+        sec += time.perf_counter() - t0
+        for dt, out in outputs.items():
+            compare_acts(acc[dt]["y"], out["y"], y, b0=b)
+        del y
+        t0 = time.perf_counter()
+        gx, gw, gwpw, gb = o.block_bwd(d1, x[b:b + 1], w, wpw, bpw, gy[b:b + 1])
+        sec += time.perf_counter() - t0
+        for dt, out in outputs.items():
+            compare_acts(acc[dt]["gx"], out["gx"], gx, b0=b)
+        del gx
+        sums = [gw, gwpw, gb] if sums is None else [sums[0] + gw, sums[1] + gwpw, sums[2] + gb]
+        log(f"[bench] oracle: batch element {b} done ({sec:.1f} s)")
+    errs = {}
+    for dt, out in outputs.items():
+        e = {k: acc[dt][k].value() for k in ("y", "gx")}
+        for k, ref in zip(("gw", "gw_pw", "gb"), sums):
+            ea = ErrAcc()
+            ea.add(out[k], ref)
+            e[k] = ea.value()
+        errs[dt] = e
     log(f"[bench] oracle: {sec:.1f} s")
-    return dict(y=y, gx=gx, gw=gw, gw_pw=gwpw, gb=gb), sec
+    return errs, sec
 
 
 def main():
@@ -296,6 +425,9 @@ def main():
     ap.add_argument("--workload", default="co2_block_128^3x32", choices=sorted(WORKLOADS))
     ap.add_argument("--no-oracle", action="store_true", help="skip the FP64 oracle (errors and cpu_baseline)")
     ap.add_argument("--no-fp32", action="store_true", help="time the BF16 path only")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the BF16 timings of the paper's own grids and the batched block")
+    ap.add_argument("--extra-steps", type=int, default=5, help="timed steps of each extra workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -315,9 +447,7 @@ def main():
 
     errs, cpu = {}, None
     if not args.no_oracle:
-        ref, sec = run_oracle(wl, data)
-        for dt_name, out in outputs.items():
-            errs[dt_name] = {k: rel(np.asarray(out[k], dtype=ref[k].dtype), ref[k]) for k in ref}
+        errs, sec = run_oracle(wl, data, outputs)
         threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
         cpu = dict(value=model_flops / sec / 1e12, unit="TFLOP/s", cores=threads, kind="oracle",
                    sample=f"one full block fwd+bwd of the benchmark workload ({args.workload}), FP64, "
@@ -326,25 +456,11 @@ def main():
     bf = results["bf16"]
     ms = bf["ms"]
     value = model_flops / (ms * 1e-3) / 1e12
-    # dominant kernel of the BF16 step and its roofline
-    kern = bf["kernels"]
-    dom = max(kern.items(), key=lambda kv: kv[1][1])
-    name, (launches, tot_ms) = dom
-    avg_ms = tot_ms / launches
-    km = kernel_model(name, B, C, C, grid, modes, 2)
-    roof = None
-    if km is not None:
-        t_hbm = km["bytes"] / (HBM_PEAK_GBS * 1e9)
-        t_mfma = km["flops"] / (MFMA_PEAK_TFLOPS["bf16"] * 1e12)
-        if t_hbm >= t_mfma:
-            ach = km["bytes"] / (avg_ms * 1e-3) / 1e9
-            roof = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                        traffic=profiled_traffic(name, "bf16", args.workload), kernel=name, avg_ms=avg_ms,
-                        bytes_per_launch=km["bytes"])
-        else:
-            ach = km["flops"] / (avg_ms * 1e-3) / 1e12
-            roof = dict(bound="mfma", achieved=ach, peak=MFMA_PEAK_TFLOPS["bf16"], unit="TFLOP/s",
-                        frac=ach / MFMA_PEAK_TFLOPS["bf16"], traffic=None, kernel=name, avg_ms=avg_ms)
+    roof = roofline_of(bf["kernels"], wl, args.workload)
+    others = {}
+    if args.workload == "co2_block_128^3x32" and not args.no_extra:
+        for name in EXTRA_WORKLOADS:
+            others[name] = run_extra(name, args.extra_steps, 2)
     line = {
         "metric": METRIC,
         "value": value,
@@ -372,6 +488,7 @@ def main():
                                 for dt, r in results.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "other_workloads": others or None,
     }
     print(json.dumps(line), flush=True)
     if errs and not line["rel_l2_within_targets"]:

@@ -96,8 +96,9 @@ int fno_plan_destroy(fno_plan_t *plan);
 
 /* Workspace bytes one call of operation `op` (FNO_OP_*) needs. */
 int fno_workspace_bytes(const fno_plan_t *plan, int op, size_t *out);
-/* Bytes of the forward cache (retained spectrum X^ and the x-inverse of Y^)
- * written by fno_spectral_fwd / fno_block_fwd and read by the backward calls.
+/* Bytes of the forward cache (the retained spectrum X^ and the y-inverse of Y^,
+ * i.e. the input of the z,t synthesis) written by fno_spectral_fwd /
+ * fno_block_fwd and read by the backward calls.
  * Precondition of every entry point that takes a non-NULL `cache`: it points to
  * at least this many bytes of device memory.  The entry points take no cache
  * size, so the library cannot check this; a shorter buffer is written or read

@@ -183,10 +183,19 @@ static WsPlan ws_plan(const Dims &d, int op)
     return w;
 }
 
+// Forward cache: the retained spectrum X^ [B Ci][nmode] complex64, then the y-inverse U1 of Y^
+// [B Co][Nx][Ny][Kz Kt] as the z,t synthesis reads it (bfloat16 pairs in the bfloat16 plan's
+// matrix-core path, complex64 otherwise), so the backward recomputes the pre-activation from it
+// without redoing the x and y inverses.
 static size_t cache_xh_bytes(const Dims &d) { return align_up(sizeof(float2) * (size_t)(d.B * d.Ci * d.nmode)); }
-static size_t cache_bytes(const Dims &d)
+static size_t cache_u1_elem(const fno_plan_t *p)
 {
-    return cache_xh_bytes(d) + align_up(sizeof(float2) * (size_t)(d.B * d.Co * d.N[0] * d.P));
+    return (p->desc.dtype == FNO_BF16 && zt_supported(p->d, FNO_BF16)) ? 4 : sizeof(float2);
+}
+static size_t cache_bytes(const fno_plan_t *p)
+{
+    const Dims &d = p->d;
+    return cache_xh_bytes(d) + align_up(cache_u1_elem(p) * (size_t)(d.B * d.Co * d.N[0] * d.N[1] * d.kplane));
 }
 
 static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
@@ -283,11 +292,10 @@ static ZtTabs zt_tabs(const fno_plan_t *p, bool adjoint)
 }
 
 // Inverse x then y stage of a retained spectrum (C channels): spec -> u2 -> u1.
-static void inverse_xy(const fno_plan_t *p, const float2 *spec, int C, float2 *u2, float2 *u1, hipStream_t st,
-                       bool skip_x = false)
+static void inverse_xy(const fno_plan_t *p, const float2 *spec, int C, float2 *u2, float2 *u1, hipStream_t st)
 {
     const Dims &d = p->d;
-    if (!skip_x) axis_stage(p, 0, false, spec, u2, (long long)d.B * C, d.P, st, "axis_inv_x");
+    axis_stage(p, 0, false, spec, u2, (long long)d.B * C, d.P, st, "axis_inv_x");
     // the y inverse feeds the z,t synthesis, which rounds it to the activation type
     axis_stage(p, 1, false, u2, u1, (long long)d.B * C * d.N[0], d.kplane, st, "axis_inv_y",
                p->desc.dtype == FNO_BF16 && zt_supported(d, FNO_BF16));
@@ -309,21 +317,22 @@ static int spectral_or_block_fwd(const fno_plan_t *p, const void *x_, const void
     char *wb = (char *)ws;
     float2 *t1 = (float2 *)(wb + wp.t1), *t2 = (float2 *)(wb + wp.t2);
     float2 *xh = cache ? (float2 *)cache : (float2 *)(wb + wp.sp);
-    float2 *u2 = cache ? (float2 *)((char *)cache + cache_xh_bytes(d)) : t2;
+    // the y-inverse of Y^ (the z,t synthesis input) goes to the cache when there is one
+    float2 *u1 = cache ? (float2 *)((char *)cache + cache_xh_bytes(d)) : t1;
     float2 *yh = (float2 *)(wb + wp.sp2);
     const T *x = (const T *)x_;
     forward_spectrum<T>(p, x, d.Ci, p->tab.wt_one, t1, t2, xh, st);
     FNO_TIMED(p, st, "mix_fwd", launch_mix_fwd(xh, (const float2 *)w_, yh, d.B, d.Ci, d.Co, d.nmode, st));
-    inverse_xy(p, yh, d.Co, u2, t1, st);
+    inverse_xy(p, yh, d.Co, t2, u1, st);
     if (zt_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
         const bool gen = zt_t_sliced(d);
         FNO_TIMED(p, st, block ? (gen ? "zt_block_tsl" : "zt_block") : (gen ? "zt_plain_tsl" : "zt_plain"),
-                  note(launch_zt<T>(block ? ZEPI_BLOCK : ZEPI_PLAIN, d, d.Co, block ? d.Ci : 0, t1, (T *)y_, x,
+                  note(launch_zt<T>(block ? ZEPI_BLOCK : ZEPI_PLAIN, d, d.Co, block ? d.Ci : 0, u1, (T *)y_, x,
                                      nullptr, (const float *)wpw, (const float *)bpw, nullptr, zt_tabs<T>(p, false), 0,
                                      st)));
     } else {
         FNO_TIMED(p, st, block ? "inv_zt_block" : "inv_zt_plain",
-                  launch_inv_zt<T>(block ? EPI_BLOCK : EPI_PLAIN, t1, (T *)y_, d.Co, d, p->tab, p->tab.wt_inv, x,
+                  launch_inv_zt<T>(block ? EPI_BLOCK : EPI_PLAIN, u1, (T *)y_, d.Co, d, p->tab, p->tab.wt_inv, x,
                                    (const float *)wpw, (const float *)bpw, nullptr, d.Ci, 0, st));
     }
     return finish();
@@ -394,17 +403,16 @@ static int block_bwd_impl(const fno_plan_t *p, const void *x_, const void *cache
     float2 *gyh = (float2 *)(wb + wp.sp2), *gxh = (float2 *)(wb + wp.sp3);
     float *gz = (float *)(wb + wp.gz), *part = (float *)(wb + wp.part);
     const float2 *xh = (const float2 *)cache;
-    const float2 *u2 = (const float2 *)((const char *)cache + cache_xh_bytes(d));
+    const float2 *u1 = (const float2 *)((const char *)cache + cache_xh_bytes(d));
     const T *x = (const T *)x_;
     const float *wpw = (const float *)wpw_, *bpw = (const float *)bpw_;
-    // recompute the pre-activation from the cached x-inverse of Y^, then gz
-    inverse_xy(p, nullptr, d.Co, const_cast<float2 *>(u2), t1, st, true);
+    // recompute the pre-activation from x and the cached y-inverse of Y^, then gz
     if (zt_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
         T *gzt = (T *)gz;  // gz stored in the activation type
         int rows_used = zt_partial_rows(d);
         const bool gen = zt_t_sliced(d);
         FNO_TIMED(p, st, gen ? "zt_bwd_tsl" : "zt_bwd",
-                  note(launch_zt<T>(ZEPI_BWD, d, d.Co, d.Ci, t1, gzt, x, (const T *)gy_, wpw, bpw, part,
+                  note(launch_zt<T>(ZEPI_BWD, d, d.Co, d.Ci, u1, gzt, x, (const T *)gy_, wpw, bpw, part,
                                      zt_tabs<T>(p, false), 0, st, &rows_used)));
         if (gwpw_ || gb_)
             FNO_TIMED(p, st, "pw_reduce",
@@ -419,7 +427,7 @@ static int block_bwd_impl(const fno_plan_t *p, const void *x_, const void *cache
                                      zt_tabs<T>(p, true), accumulate, st)));
         return finish();
     }
-    FNO_TIMED(p, st, "bwd_gz", launch_bwd_gz<T>(t1, x, (const T *)gy_, gz, d, p->tab, wpw, bpw, st));
+    FNO_TIMED(p, st, "bwd_gz", launch_bwd_gz<T>(u1, x, (const T *)gy_, gz, d, p->tab, wpw, bpw, st));
     if (gwpw_ || gb_)
         FNO_TIMED(p, st, "pw_wgrad",
                   launch_pw_wgrad<T>(gz, x, part, (float *)gwpw_, (float *)gb_, d.B, d.Ci, d.Co, d.ncell, accumulate,
@@ -602,7 +610,7 @@ int fno_workspace_bytes(const fno_plan_t *plan, int op, size_t *out)
 int fno_cache_bytes(const fno_plan_t *plan, size_t *out)
 {
     if (!plan || !out) return FNO_ERR_INVALID_ARG;
-    *out = cache_bytes(plan->d);
+    *out = cache_bytes(plan);
     return FNO_OK;
 }
 

@@ -104,80 +104,96 @@ __global__ void k_mix_bwd_w(const float2 *__restrict__ xh, const float2 *__restr
     }
 }
 
-// Tiled mix: a workgroup owns 64 consecutive retained modes; the batch's X^ (or gY^) of all
-// channels at those modes is staged in LDS once, and the 4 groups of 64 lanes split the output
-// channels, so every W element is read once (and, in the backward, gW written once) in
-// coalesced 512-byte rows while X^ / gY^ are read once.
-constexpr int kMixK = 64;
+// Tiled mix: a workgroup owns KM (64 or 32) consecutive retained modes; the batch's X^ (or gY^)
+// of all channels at those modes is staged in LDS once, and the 256 / KM groups of KM lanes split
+// the output channels.  The batch is held in registers (BM >= B), so every W element is read
+// once (and, in the backward, gW written once) in coalesced rows of KM complex values while X^ /
+// gY^ are read once.
 
 // Y^[b][o][k] = sum_i X^[b][i][k] W[i][o][k]
+template <int KM, int BM>
 __global__ void __launch_bounds__(256) k_mix_fwd_t(const float2 *__restrict__ xh, const float2 *__restrict__ w,
                                                    float2 *__restrict__ yh, int B, int Ci, int Co, long long M)
 {
-    extern __shared__ float2 xs[];  // [b][i][kMixK]
-    const int tk = threadIdx.x % kMixK, to = threadIdx.x / kMixK;
-    const long long k0 = (long long)blockIdx.x * kMixK, k = k0 + tk;
-    for (int e = threadIdx.x; e < B * Ci * kMixK; e += 256) {
-        const int bi = e / kMixK, kk = e % kMixK;
+    constexpr int NG = 256 / KM;
+    extern __shared__ float2 xs[];  // [b][i][KM]
+    const int tk = threadIdx.x % KM, to = threadIdx.x / KM;
+    const long long k0 = (long long)blockIdx.x * KM, k = k0 + tk;
+    for (int e = threadIdx.x; e < B * Ci * KM; e += 256) {
+        const int bi = e / KM, kk = e % KM;
         xs[e] = k0 + kk < M ? xh[(long long)bi * M + k0 + kk] : make_float2(0.f, 0.f);
     }
     __syncthreads();
     if (k >= M) return;
-    for (int o = to; o < Co; o += 4)
-        for (int b = 0; b < B; b++) {
-            float re = 0.f, im = 0.f;
-            for (int i = 0; i < Ci; i++) {
-                const float2 a = xs[(b * Ci + i) * kMixK + tk];
-                const float2 q = w[((long long)i * Co + o) * M + k];
-                re += a.x * q.x - a.y * q.y;
-                im += a.x * q.y + a.y * q.x;
-            }
-            yh[((long long)b * Co + o) * M + k] = make_float2(re, im);
+    for (int o = to; o < Co; o += NG) {
+        float re[BM], im[BM];
+#pragma unroll
+        for (int b = 0; b < BM; b++) re[b] = im[b] = 0.f;
+        for (int i = 0; i < Ci; i++) {
+            const float2 q = w[((long long)i * Co + o) * M + k];
+#pragma unroll
+            for (int b = 0; b < BM; b++)
+                if (b < B) {
+                    const float2 a = xs[(b * Ci + i) * KM + tk];
+                    re[b] += a.x * q.x - a.y * q.y;
+                    im[b] += a.x * q.y + a.y * q.x;
+                }
         }
+#pragma unroll
+        for (int b = 0; b < BM; b++)
+            if (b < B) yh[((long long)b * Co + o) * M + k] = make_float2(re[b], im[b]);
+    }
 }
 
 // gX^[b][i][k] = sum_o gY^[b][o][k] conj(W[i][o][k]) and gW[i][o][k] (+)= sum_b conj(X^[b][i][k]) gY^[b][o][k],
 // one pass over W and gW (either output may be null; with gw null, xh may be null).
+template <int KM, int BM>
 __global__ void __launch_bounds__(256) k_mix_bwd_t(const float2 *__restrict__ xh, const float2 *__restrict__ w,
                                                    const float2 *__restrict__ gyh, float2 *__restrict__ gxh,
                                                    float2 *__restrict__ gw, int B, int Ci, int Co, long long M,
                                                    int accumulate)
 {
-    extern __shared__ float2 sh[];  // gs [b][o][kMixK], then xs [b][i][kMixK]
-    float2 *gs = sh, *xs = sh + (size_t)B * Co * kMixK;
-    const int tk = threadIdx.x % kMixK, ti = threadIdx.x / kMixK;
-    const long long k0 = (long long)blockIdx.x * kMixK, k = k0 + tk;
-    for (int e = threadIdx.x; e < B * Co * kMixK; e += 256) {
-        const int bo = e / kMixK, kk = e % kMixK;
+    constexpr int NG = 256 / KM;
+    extern __shared__ float2 sh[];  // gs [b][o][KM], then xs [b][i][KM]
+    float2 *gs = sh, *xs = sh + (size_t)B * Co * KM;
+    const int tk = threadIdx.x % KM, ti = threadIdx.x / KM;
+    const long long k0 = (long long)blockIdx.x * KM, k = k0 + tk;
+    for (int e = threadIdx.x; e < B * Co * KM; e += 256) {
+        const int bo = e / KM, kk = e % KM;
         gs[e] = k0 + kk < M ? gyh[(long long)bo * M + k0 + kk] : make_float2(0.f, 0.f);
     }
     if (gw)
-        for (int e = threadIdx.x; e < B * Ci * kMixK; e += 256) {
-            const int bi = e / kMixK, kk = e % kMixK;
+        for (int e = threadIdx.x; e < B * Ci * KM; e += 256) {
+            const int bi = e / KM, kk = e % KM;
             xs[e] = k0 + kk < M ? xh[(long long)bi * M + k0 + kk] : make_float2(0.f, 0.f);
         }
     __syncthreads();
     if (k >= M) return;
-    for (int i = ti; i < Ci; i += 4) {
-        for (int b = 0; b < (gxh ? B : 0); b++) {
-            float re = 0.f, im = 0.f;
-            for (int o = 0; o < Co; o++) {
-                const float2 g = gs[(b * Co + o) * kMixK + tk];
-                const float2 q = w[((long long)i * Co + o) * M + k];
-                re += g.x * q.x + g.y * q.y;
-                im += g.y * q.x - g.x * q.y;
+    for (int i = ti; i < Ci; i += NG) {
+        float gre[BM], gim[BM];
+#pragma unroll
+        for (int b = 0; b < BM; b++) gre[b] = gim[b] = 0.f;
+        for (int o = 0; o < Co; o++) {
+            const long long wi = ((long long)i * Co + o) * M + k;
+            if (gxh) {
+                const float2 q = w[wi];
+#pragma unroll
+                for (int b = 0; b < BM; b++)
+                    if (b < B) {
+                        const float2 g = gs[(b * Co + o) * KM + tk];
+                        gre[b] += g.x * q.x + g.y * q.y;
+                        gim[b] += g.y * q.x - g.x * q.y;
+                    }
             }
-            gxh[((long long)b * Ci + i) * M + k] = make_float2(re, im);
-        }
-        if (gw)
-            for (int o = 0; o < Co; o++) {
+            if (gw) {
                 float re = 0.f, im = 0.f;
-                for (int b = 0; b < B; b++) {
-                    const float2 a = xs[(b * Ci + i) * kMixK + tk], g = gs[(b * Co + o) * kMixK + tk];
-                    re += a.x * g.x + a.y * g.y;
-                    im += a.x * g.y - a.y * g.x;
-                }
-                const long long wi = ((long long)i * Co + o) * M + k;
+#pragma unroll
+                for (int b = 0; b < BM; b++)
+                    if (b < B) {
+                        const float2 a = xs[(b * Ci + i) * KM + tk], g = gs[(b * Co + o) * KM + tk];
+                        re += a.x * g.x + a.y * g.y;
+                        im += a.x * g.y - a.y * g.x;
+                    }
                 if (accumulate) {
                     const float2 p0 = gw[wi];
                     re += p0.x;
@@ -185,6 +201,12 @@ __global__ void __launch_bounds__(256) k_mix_bwd_t(const float2 *__restrict__ xh
                 }
                 gw[wi] = make_float2(re, im);
             }
+        }
+        if (gxh) {
+#pragma unroll
+            for (int b = 0; b < BM; b++)
+                if (b < B) gxh[((long long)b * Ci + i) * M + k] = make_float2(gre[b], gim[b]);
+        }
     }
 }
 
@@ -273,26 +295,57 @@ void launch_axis(const float2 *in, float2 *out, const float2 *tab, long long out
                        Nout, inner, N, inverse);
 }
 
+// Tiled mix launch: the mode tile (64, else 32) whose LDS stage fits 64 KB, for B <= 8; 0 if none.
+static int mix_tile(int B, int C)
+{
+    if (B > 8) return 0;
+    if (sizeof(float2) * (size_t)B * C * 64 <= 64 * 1024) return 64;
+    if (sizeof(float2) * (size_t)B * C * 32 <= 64 * 1024) return 32;
+    return 0;
+}
+
+template <int KM>
+static void launch_mix_fwd_km(const float2 *xh, const float2 *w, float2 *yh, int B, int Ci, int Co, long long M,
+                              hipStream_t st)
+{
+    const size_t lds = sizeof(float2) * (size_t)B * Ci * KM;
+    const dim3 grid((unsigned)((M + KM - 1) / KM));
+    if (B <= 1) hipLaunchKernelGGL((k_mix_fwd_t<KM, 1>), grid, dim3(256), lds, st, xh, w, yh, B, Ci, Co, M);
+    else if (B <= 2) hipLaunchKernelGGL((k_mix_fwd_t<KM, 2>), grid, dim3(256), lds, st, xh, w, yh, B, Ci, Co, M);
+    else if (B <= 4) hipLaunchKernelGGL((k_mix_fwd_t<KM, 4>), grid, dim3(256), lds, st, xh, w, yh, B, Ci, Co, M);
+    else hipLaunchKernelGGL((k_mix_fwd_t<KM, 8>), grid, dim3(256), lds, st, xh, w, yh, B, Ci, Co, M);
+}
+
 void launch_mix_fwd(const float2 *xh, const float2 *w, float2 *yh, int B, int Ci, int Co, long long M, hipStream_t st)
 {
-    const size_t lds = sizeof(float2) * (size_t)B * Ci * kMixK;
-    if (lds <= 64 * 1024) {
-        hipLaunchKernelGGL(k_mix_fwd_t, dim3((unsigned)((M + kMixK - 1) / kMixK)), dim3(256), lds, st, xh, w, yh, B, Ci,
-                           Co, M);
-        return;
-    }
+    const int km = mix_tile(B, Ci);
+    if (km == 64) return launch_mix_fwd_km<64>(xh, w, yh, B, Ci, Co, M, st);
+    if (km == 32) return launch_mix_fwd_km<32>(xh, w, yh, B, Ci, Co, M, st);
     hipLaunchKernelGGL(k_mix_fwd, dim3(grid_for((long long)B * Co * M, 256)), dim3(256), 0, st, xh, w, yh, B, Ci, Co, M);
+}
+
+template <int KM>
+static void launch_mix_bwd_km(const float2 *xh, const float2 *w, const float2 *gyh, float2 *gxh, float2 *gw, int B,
+                              int Ci, int Co, long long M, int accumulate, hipStream_t st)
+{
+    const size_t lds = sizeof(float2) * (size_t)B * (Co + (gw ? Ci : 0)) * KM;
+    const dim3 grid((unsigned)((M + KM - 1) / KM));
+#define FNO_MIX_BWD(BM_)                                                                                         \
+    hipLaunchKernelGGL((k_mix_bwd_t<KM, BM_>), grid, dim3(256), lds, st, xh, w, gyh, gxh, gw, B, Ci, Co, M,     \
+                       accumulate)
+    if (B <= 1) FNO_MIX_BWD(1);
+    else if (B <= 2) FNO_MIX_BWD(2);
+    else if (B <= 4) FNO_MIX_BWD(4);
+    else FNO_MIX_BWD(8);
+#undef FNO_MIX_BWD
 }
 
 void launch_mix_bwd(const float2 *xh, const float2 *w, const float2 *gyh, float2 *gxh, float2 *gw, int B, int Ci,
                     int Co, long long M, int accumulate, hipStream_t st)
 {
-    const size_t lds = sizeof(float2) * (size_t)B * (Co + (gw ? Ci : 0)) * kMixK;
-    if (lds <= 64 * 1024) {
-        hipLaunchKernelGGL(k_mix_bwd_t, dim3((unsigned)((M + kMixK - 1) / kMixK)), dim3(256), lds, st, xh, w, gyh, gxh,
-                           gw, B, Ci, Co, M, accumulate);
-        return;
-    }
+    const int km = mix_tile(B, Co + (gw ? Ci : 0));
+    if (km == 64) return launch_mix_bwd_km<64>(xh, w, gyh, gxh, gw, B, Ci, Co, M, accumulate, st);
+    if (km == 32) return launch_mix_bwd_km<32>(xh, w, gyh, gxh, gw, B, Ci, Co, M, accumulate, st);
     if (gxh)
         hipLaunchKernelGGL(k_mix_bwd_x, dim3(grid_for((long long)B * Ci * M, 256)), dim3(256), 0, st, gyh, w, gxh, B,
                            Ci, Co, M);

@@ -52,6 +52,9 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3, ZEPI_ADJ_ACC 
 #ifndef FNO_ZT_ZC_BF16
 #define FNO_ZT_ZC_BF16 16  // z values per chunk in the bfloat16 kernels (8 or 16; 8 measured slower)
 #endif
+#ifndef FNO_ZT_FILL_ONE
+#define FNO_ZT_FILL_ONE 1  // a workgroup alone on its CU (LDS) takes up to 16 waves
+#endif
 #ifndef FNO_ZT_GELU_BWD
 #define FNO_ZT_GELU_BWD 1  // bfloat16 BWD GELU': 0 A&S 7.1.26, 1 logistic Phi + exact phi, 2 logistic derivative
 #endif
@@ -194,6 +197,42 @@ __device__ __forceinline__ s4v op_gather(const __bf16 *p, int stride)
 }
 
 template <int EPI> constexpr bool has_src_c() { return EPI != ZEPI_PLAIN; }
+
+// phase 2 for the current z chunk (and t slice): every tile of this wave.  With AHEAD, group j
+// of this wave has its epilogue operand loaded one z chunk ahead (gi is hidden from the
+// optimiser, or the LDS addresses of all JM tiles are hoisted out of the chunk loop and held
+// in registers throughout); otherwise the next tile's operand is loaded before each tile.
+// (A macro rather than a lambda: called through a lambda, the loop compiled into the tuned
+// kernels with more register copies and waits per tile, and ran about 10% slower.)
+#define FNO_ZT_PHASE2()                                                                \
+    do {                                                                               \
+            if constexpr (AHEAD) {                                                     \
+_Pragma("unroll")                                                                      \
+                for (int j = 0; j < JM; j++) {                                         \
+                    int gi = tr + j * R;                                               \
+                    asm volatile("" : "+s"(gi));                                       \
+                    if (gi < ngroups) {                                                \
+                        const int z0 = zc0 + gi * ZG;                                  \
+                        if (z0 < Nz) tile(gi, z0, ext[j]);                             \
+                        if (zc0 + ZC < Nz) load_ext(ecol, z0 + ZC, ext[j]);            \
+                        else load_ext(ecol_n, has_next ? gi * ZG : Nz, ext[j]);        \
+                    }                                                                  \
+                }                                                                      \
+            } else {                                                                   \
+                for (int gi = tr; gi < ngroups; gi += R) {                             \
+                    const int z0 = zc0 + gi * ZG;                                      \
+                    if (z0 >= Nz) break;                                               \
+                    Op en[NTQ];                                                        \
+                    if (EXT) load_ext(ecol, gi + R < ngroups ? z0 + R * ZG : Nz, en);  \
+                    tile(gi, z0, ext[0]);                                              \
+                    if (EXT) {                                                         \
+_Pragma("unroll")                                                                      \
+                        for (int mt = 0; mt < NTQ; mt++) ext[0][mt] = en[mt];          \
+                    }                                                                  \
+                }                                                                      \
+            }                                                                          \
+    } while (0)
+
 
 // NTT: (re/im, kt) tiles (1: Kt <= 8, 2: Kt <= 16).  NTQ: t tiles (1: Nt <= 16, 2: Nt <= 32).
 // SPAN: source K chunks every tile multiplies (weight fragments beyond a tile's own chunks are zero).
@@ -685,36 +724,6 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                     }
                 }
             };
-            auto phase2 = [&]() {
-            if constexpr (AHEAD) {
-#pragma unroll
-                for (int j = 0; j < JM; j++) {
-                    // gi is the same in every chunk: hide that, or the LDS addresses of all JM
-                    // tiles are hoisted out of the chunk loop and held in registers throughout
-                    int gi = tr + j * R;
-                    asm volatile("" : "+s"(gi));
-                    if (gi < ngroups) {
-                        const int z0 = zc0 + gi * ZG;
-                        if (z0 < Nz) tile(gi, z0, ext[j]);
-                        // the same group of the next chunk, else of the next plane's first chunk
-                        if (zc0 + ZC < Nz) load_ext(ecol, z0 + ZC, ext[j]);
-                        else load_ext(ecol_n, has_next ? gi * ZG : Nz, ext[j]);
-                    }
-                }
-            } else {
-                for (int gi = tr; gi < ngroups; gi += R) {
-                    const int z0 = zc0 + gi * ZG;
-                    if (z0 >= Nz) break;
-                    Op en[NTQ];
-                    if (EXT) load_ext(ecol, gi + R < ngroups ? z0 + R * ZG : Nz, en);
-                    tile(gi, z0, ext[0]);
-                    if (EXT) {
-#pragma unroll
-                        for (int mt = 0; mt < NTQ; mt++) ext[0][mt] = en[mt];
-                    }
-                }
-            }
-            };
             if constexpr (GEN) {
                 for (int ts = 0; ts < a.NS; ts++) {
                     tofs = 16 * NTQ * ts;
@@ -723,11 +732,11 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                     load_ta(ts);
                     if (EXT) load_ext(ecol, zc0 + tr * ZG, ext[0]);
                     __syncthreads();  // V and the slice's source rows staged
-                    phase2();
+                    FNO_ZT_PHASE2();
                 }
             } else {
                 __syncthreads();  // V staged
-                phase2();
+                FNO_ZT_PHASE2();
             }
         }
     }
@@ -849,17 +858,29 @@ static size_t zt_layout_zc(const Dims &d, int Cs, int Csrc, int elem, int target
 
 // Layout with 16-z chunks (the bfloat16 default may be 8), or with 8-z chunks where 16 would need
 // more LDS than a workgroup has (wide float planes: the V chunk and the transposed source halve).
+// Where the LDS admits a single workgroup per CU (float planes at width 20, the batched block's
+// width-32 planes), that workgroup takes up to 16 waves instead of the target (the tile indices
+// per group allow it): with 4 or 5 waves the CU had one wave per SIMD to hide every latency with.
 static size_t zt_layout(const Dims &d, int Cs, int Csrc, int elem, int target, bool ext, ZtArgs &a)
 {
     const int zg = 16 / gcd_int(Cs, 16);
-    const int zc = (elem == 2 && zg <= FNO_ZT_ZC_BF16) ? FNO_ZT_ZC_BF16 : 16;
-    const size_t lds = zt_layout_zc(d, Cs, Csrc, elem, target, ext, zc, a);
+    int zc = (elem == 2 && zg <= FNO_ZT_ZC_BF16) ? FNO_ZT_ZC_BF16 : 16;
+    size_t lds = zt_layout_zc(d, Cs, Csrc, elem, target, ext, zc, a);
     if ((lds == 0 || lds > 160 * 1024) && zc == 16 && zg <= 8) {
         ZtArgs a8;
         const size_t lds8 = zt_layout_zc(d, Cs, Csrc, elem, target, ext, 8, a8);
         if (lds8 != 0 && lds8 <= 160 * 1024) {
             a = a8;
-            return lds8;
+            lds = lds8;
+            zc = 8;
+        }
+    }
+    if (FNO_ZT_FILL_ONE && lds != 0 && lds <= 160 * 1024 && 2 * lds > 160 * 1024 && a.NT * a.R < kZtMaxWaves) {
+        ZtArgs aw;
+        const size_t ldsw = zt_layout_zc(d, Cs, Csrc, elem, kZtMaxWaves, ext, zc, aw);
+        if (ldsw != 0 && ldsw <= 160 * 1024) {
+            a = aw;
+            lds = ldsw;
         }
     }
     return lds;

@@ -48,6 +48,9 @@ SHAPES = {
     # kernels take (the scalar kernels)
     "odd_t45": (1, 3, 5, (4, 5, 20, 45), (2, 2, 5, 12)),
     "scalar_kt21": (1, 2, 3, (4, 4, 6, 40), (2, 2, 3, 21)),
+    # batch 4 at width 32 (the batched CO2 block's): the mix holds the batch in registers and
+    # its backward takes 32-mode tiles (64 would not fit in LDS)
+    "batch4_w32": (4, 32, 32, (4, 4, 16, 8), (2, 2, 4, 4)),
 }
 
 # the kernels each shape must run on: forward t,z,y (k_tzy_fwd "tzy_fwd", the general
@@ -70,6 +73,7 @@ PATHS = {
     "co2_true_w20": ("tzy_gen", "zt_block_tsl"),
     "odd_t45": ("tzy_gen", "zt_block_tsl"),
     "scalar_kt21": ("fwd_tz", "inv_zt_block"),
+    "batch4_w32": ("tzy_fwd", "zt_block"),
 }
 
 
