@@ -48,7 +48,11 @@ WORKLOADS = {
 }
 # timed beside the headline in a default run (BF16 only, device-generated inputs, no oracle: their
 # parity is tested at reduced grids that run the same kernel variants)
-EXTRA_WORKLOADS = ("ns_true_130^3x64", "co2_true_262x118x64x86", "co2_batched_block_128^3x32")
+EXTRA_WORKLOADS = ("ns_true_130^3x64", "co2_true_262x118x64x86", "co2_batched_block_128^3x32",
+                   "co2_block_128^3x32+w_fp8", "co2_batched_block_128^3x32+w_fp8")
+# "+w_fp8": the plan takes the spectral weights packed as OCP E4M3 with per-channel-pair scales
+# (FNO_W_FP8); the step packs them (fno_pack_weights) before the block fwd+bwd, as a training
+# step whose weights change every step must.
 
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"bf16": 2500.0, "f32": 157.3}
@@ -258,13 +262,16 @@ def run_extra(name, steps, warmup):
 
     from paper_2211_12709_amd import fno, inputs
 
-    B, C, grid, modes = WORKLOADS[name]
+    base, _, variant = name.partition("+")
+    fp8 = variant == "w_fp8"
+    B, C, grid, modes = WORKLOADS[base]
     dev = torch.device("cuda", 0)
     ksh = (2 * modes[0], 2 * modes[1], 2 * modes[2], modes[3])
     log(f"[bench] {name}: B={B} C={C} grid={grid} modes={modes}")
     g = torch.Generator(device=dev)
     g.manual_seed(inputs.SEED_INPUT)
-    plan = fno.Plan(B, C, C, grid, modes, fno.FNO_BF16)
+    plan = fno.Plan(B, C, C, grid, modes, fno.FNO_BF16, fno.FNO_W_FP8 if fp8 else 0)
+    packed = torch.empty(plan.packed_weight_bytes(), dtype=torch.uint8, device=dev) if fp8 else None
     xa = torch.randn((B, C, *grid), generator=g, device=dev, dtype=torch.bfloat16)
     gya = torch.randn((B, C, *grid), generator=g, device=dev, dtype=torch.bfloat16)
     tw = torch.randn((C, C, *ksh), generator=g, device=dev, dtype=torch.complex64) / C
@@ -277,19 +284,65 @@ def run_extra(name, steps, warmup):
     gb = torch.empty_like(tb)
 
     def step():
-        plan.block_fwd(xa, tw, twp, tb, y=y, cache=cache)
-        plan.block_bwd(xa, cache, tw, twp, tb, gya, gx=gx, gw=gw, gw_pw=gwpw, gb_pw=gb)
+        wv = plan.pack_weights(tw, packed) if fp8 else tw
+        plan.block_fwd(xa, wv, twp, tb, y=y, cache=cache)
+        plan.block_bwd(xa, cache, wv, twp, tb, gya, gx=gx, gw=gw, gw_pw=gwpw, gb_pw=gb)
 
     r = time_steps(step, steps, warmup, 1, plan)
     fm = flop_model(B, C, C, grid, modes)
-    wl = WORKLOADS[name]
+    wl = WORKLOADS[base]
     out = dict(config={"batch": B, "width": C, "grid": list(grid), "modes": list(modes)}, dtype="bf16",
                ms_per_step=r["ms"], median_ms_per_step=r["median_ms"], ci95_ms_per_step=r["ci95_ms"],
                tflops=(fm["fwd"] + fm["bwd"]) / (r["ms"] * 1e-3) / 1e12,
                kernels_ms_per_step={k: v[1] for k, v in r["kernels"].items()},
-               roofline=roofline_of(r["kernels"], wl, name), data="synthetic (device normal draws)")
+               roofline=roofline_of(r["kernels"], wl, base), data="synthetic (device normal draws)")
     log(f"[bench] {name}: {r['ms']:.3f} ms/step")
     del plan, xa, gya, cache, y, gx, tw, gw
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_network_leg(steps, warmup):
+    """BF16 training step of the CO2-shaped 4-block FNO (Alg. 1) at 128^3 x 32: the 3-channel
+    CO2-like input (ln k, porosity, injection-well column; paper_2211_12709_amd.inputs), lifting
+    to width 20, four blocks with modes 16,16,16,8 (per-block recomputation in the backward),
+    projection 20 -> 128 -> 1, MSE against a seeded target; seeded weights.  No oracle (the
+    network's parity is tested at full size on the Navier-Stokes-shaped grid)."""
+    import torch
+
+    from paper_2211_12709_amd import fno, inputs
+
+    B, C, grid, modes = WORKLOADS["co2_block_128^3x32"]
+    dev = torch.device("cuda", 0)
+    ksh = (2 * modes[0], 2 * modes[1], 2 * modes[2], modes[3])
+    log(f"[bench] co2_network_128^3x32: 4 blocks, width {C}, grid {grid}, modes {modes}")
+    we, be = inputs.linear_weights(C, 3, seed=inputs.SEED_LIFT)
+    blocks = [inputs.block_params(C, C, ksh, block=i) for i in range(4)]
+    w1, b1 = inputs.linear_weights(128, C, seed=inputs.SEED_PROJ1)
+    w2, b2 = inputs.linear_weights(1, 128, seed=inputs.SEED_PROJ2)
+    params = {"lift": (we, be), "blocks": blocks, "proj": (w1, b1, w2, b2)}
+    net = fno.FNO4d(3, C, grid, modes, nblocks=4, dtype=torch.bfloat16, params=params)
+    x = torch.from_numpy(inputs.co2_like_input(1, grid)).to(dev).to(torch.bfloat16)
+    g = torch.Generator(device=dev)
+    g.manual_seed(inputs.SEED_TARGET)
+    target = torch.randn((1, 1, *grid), generator=g, device=dev).to(torch.bfloat16)
+
+    def step():
+        for p_ in net.parameters():
+            p_.grad = None
+        loss = fno.MseFn.apply(net(x), target)
+        loss.backward()
+
+    r = time_steps(step, steps, warmup, 1, net.plan)
+    fm = flop_model(B, C, C, grid, modes)
+    out = dict(config={"batch": B, "width": C, "grid": list(grid), "modes": list(modes), "blocks": 4,
+                       "lift": [3, C], "projection": [C, 128, 1]}, dtype="bf16",
+               ms_per_step=r["ms"], median_ms_per_step=r["median_ms"], ci95_ms_per_step=r["ci95_ms"],
+               block_tflops=4 * (fm["fwd"] + fm["bwd"]) / (r["ms"] * 1e-3) / 1e12,
+               kernels_ms_per_step={k: v[1] for k, v in r["kernels"].items()},
+               data="synthetic (CO2-like input fields, device normal target)")
+    log(f"[bench] co2_network_128^3x32: {r['ms']:.3f} ms/step")
+    del net, x, target
     torch.cuda.empty_cache()
     return out
 
@@ -461,6 +514,7 @@ def main():
     if args.workload == "co2_block_128^3x32" and not args.no_extra:
         for name in EXTRA_WORKLOADS:
             others[name] = run_extra(name, args.extra_steps, 2)
+        others["co2_network_128^3x32"] = run_network_leg(args.extra_steps, 2)
     line = {
         "metric": METRIC,
         "value": value,

@@ -62,6 +62,14 @@ typedef enum {
 
 enum { FNO_F32 = 0, FNO_BF16 = 1 };
 
+/* Descriptor flags.
+ * FNO_W_FP8: the spectral weights `w` taken by fno_spectral_fwd/bwd and fno_block_fwd/bwd are the
+ *   packed 8-bit form written by fno_pack_weights (OCP E4M3 values with one power-of-two scale
+ *   per (c_in, c_out) pair) instead of complex float; the mode mix (Alg. 2, line 2) reads 2 bytes
+ *   per complex weight instead of 8.  Weight gradients stay complex float.  Requires batch <= 8
+ *   and a mode tile of the mix that fits in LDS (FNO_ERR_UNSUPPORTED otherwise). */
+enum { FNO_W_FP8 = 1u << 0 };
+
 enum {
     FNO_OP_SPECTRAL_FWD = 0,
     FNO_OP_SPECTRAL_BWD = 1,
@@ -72,7 +80,7 @@ enum {
 /* Problem descriptor: the arguments of the layer in Sec. IV-C -- batch,
  * channels, grid (x, y, z, t), retained modes per axis.
  * Requires B, C_in, C_out, grid[d], modes[d] >= 1; 2*modes[d] <= grid[d] for
- * d = x, y, z; modes[3] <= grid[3]/2 + 1.  flags must be 0 (reserved). */
+ * d = x, y, z; modes[3] <= grid[3]/2 + 1.  flags: 0 or FNO_W_FP8. */
 typedef struct {
     int32_t B, C_in, C_out;
     int32_t grid[4];  /* Nx, Ny, Nz, Nt */
@@ -104,6 +112,18 @@ int fno_workspace_bytes(const fno_plan_t *plan, int op, size_t *out);
  * size, so the library cannot check this; a shorter buffer is written or read
  * out of bounds on the device. */
 int fno_cache_bytes(const fno_plan_t *plan, size_t *out);
+
+/* Bytes of the packed 8-bit form of a plan's spectral weights:
+ * [C_in][C_out][2mx][2my][2mz][mt] 16-bit words (low byte the real part, high byte the imaginary
+ * part, each an OCP E4M3 value), then, at the next 256-byte boundary, [C_in][C_out] float scales,
+ * then scratch that fno_pack_weights uses for its per-chunk sums. */
+int fno_packed_weight_bytes(const fno_plan_t *plan, size_t *out);
+/* Packs complex float weights w ([C_in][C_out][modes], as for the other entry points) into wq:
+ * for every (c_in, c_out) pair, s = 2^round(log2 RMS) over the real and imaginary parts of its
+ * weights, and each part stored as the E4M3 value nearest to part / s (ties to even, magnitudes
+ * above 448 saturating).  Enqueued on `stream`; FNO_ERR_WORKSPACE if wq_bytes is smaller than
+ * fno_packed_weight_bytes.  Any plan can pack; FNO_W_FP8 plans consume the result. */
+int fno_pack_weights(const fno_plan_t *plan, const void *w, void *wq, size_t wq_bytes, void *stream);
 
 /* Spectral convolution layer (Alg. 2): y = S(x; w).  cache (nullable)
  * receives what the backward needs. */

@@ -21,9 +21,15 @@ namespace fno {
 hipError_t generate_tables(const Dims &d, Tables &t, hipStream_t st);
 void launch_axis(const float2 *in, float2 *out, const float2 *tab, long long outer, int Nin, int Nout,
                  long long inner, int N, int inverse, hipStream_t st);
-void launch_mix_fwd(const float2 *xh, const float2 *w, float2 *yh, int B, int Ci, int Co, long long M, hipStream_t st);
-void launch_mix_bwd(const float2 *xh, const float2 *w, const float2 *gyh, float2 *gxh, float2 *gw, int B, int Ci,
-                    int Co, long long M, int accumulate, hipStream_t st);
+void launch_mix_fwd(const float2 *xh, const float2 *w, const unsigned short *wq, const float *wscale, float2 *yh,
+                    int B, int Ci, int Co, long long M, hipStream_t st);
+void launch_mix_bwd(const float2 *xh, const float2 *w, const unsigned short *wq, const float *wscale,
+                    const float2 *gyh, float2 *gxh, float2 *gw, int B, int Ci, int Co, long long M, int accumulate,
+                    hipStream_t st);
+bool mix_tiled(int B, int Ci, int Co);
+size_t packed_weight_bytes(int Ci, int Co, long long M);
+size_t packed_scale_offset(int Ci, int Co, long long M);
+hipError_t launch_pack_w_fp8(const float2 *w, void *wq, int Ci, int Co, long long M, hipStream_t st);
 int pw_wgrad_chunks(long long total);
 template <typename T>
 void launch_pw_wgrad(const float *gz, const T *x, float *part, float *gwpw, float *gb, int B, int Ci, int Co,
@@ -137,7 +143,7 @@ static int dims_from_desc(const fno_desc_t *s, Dims *d)
         if (2LL * s->modes[a] > s->grid[a]) return FNO_ERR_INVALID_ARG;
     if (s->modes[3] > s->grid[3] / 2 + 1) return FNO_ERR_INVALID_ARG;
     if (s->dtype != FNO_F32 && s->dtype != FNO_BF16) return FNO_ERR_UNSUPPORTED;
-    if (s->flags != 0) return FNO_ERR_UNSUPPORTED;
+    if (s->flags & ~(uint32_t)FNO_W_FP8) return FNO_ERR_UNSUPPORTED;
     d->B = s->B;
     d->Ci = s->C_in;
     d->Co = s->C_out;
@@ -155,6 +161,8 @@ static int dims_from_desc(const fno_desc_t *s, Dims *d)
     if (d->Ci > kMaxChannels || d->Co > kMaxChannels) return FNO_ERR_UNSUPPORTED;
     if (fwd_tz_lds(*d) > kMaxLds || inv_zt_lds(*d) > kMaxLds) return FNO_ERR_UNSUPPORTED;
     if ((long long)d->B * std::max(d->Ci, d->Co) * d->N[0] * d->N[1] > 0x7fffffffLL) return FNO_ERR_UNSUPPORTED;
+    // packed weights are read by the tiled mix kernels only
+    if ((s->flags & FNO_W_FP8) && !mix_tiled(d->B, d->Ci, d->Co)) return FNO_ERR_UNSUPPORTED;
     return FNO_OK;
 }
 
@@ -246,6 +254,22 @@ static void axis_stage(const fno_plan_t *p, int ax, bool forward, const float2 *
     }
 }
 
+// The spectral weights as the mix reads them: complex64, or (FNO_W_FP8 plans) the packed e4m3
+// words and their per-channel-pair scales.
+struct MixW {
+    const float2 *w;
+    const unsigned short *q;
+    const float *scale;
+};
+static MixW mix_w(const fno_plan_t *p, const void *w)
+{
+    const Dims &d = p->d;
+    if (p->desc.flags & FNO_W_FP8)
+        return MixW{nullptr, (const unsigned short *)w,
+                    (const float *)((const char *)w + packed_scale_offset(d.Ci, d.Co, d.nmode))};
+    return MixW{(const float2 *)w, nullptr, nullptr};
+}
+
 template <typename T>
 static TzyTabs tzy_tabs(const fno_plan_t *p, const float *wt)
 {
@@ -322,7 +346,8 @@ static int spectral_or_block_fwd(const fno_plan_t *p, const void *x_, const void
     float2 *yh = (float2 *)(wb + wp.sp2);
     const T *x = (const T *)x_;
     forward_spectrum<T>(p, x, d.Ci, p->tab.wt_one, t1, t2, xh, st);
-    FNO_TIMED(p, st, "mix_fwd", launch_mix_fwd(xh, (const float2 *)w_, yh, d.B, d.Ci, d.Co, d.nmode, st));
+    const MixW mw = mix_w(p, w_);
+    FNO_TIMED(p, st, "mix_fwd", launch_mix_fwd(xh, mw.w, mw.q, mw.scale, yh, d.B, d.Ci, d.Co, d.nmode, st));
     inverse_xy(p, yh, d.Co, t2, u1, st);
     if (zt_supported(d, sizeof(T) == 2 ? FNO_BF16 : FNO_F32)) {
         const bool gen = zt_t_sliced(d);
@@ -367,7 +392,8 @@ static int spectral_bwd_impl(const fno_plan_t *p, const void *x_, const void *ca
     // adjoint of the real inverse: gY^ = (c(kt)/N) sum_n gy exp(-i theta)
     forward_spectrum<T>(p, (const T *)gy_, d.Co, p->tab.wt_inv, t1, t2, gyh, st);
     FNO_TIMED(p, st, "mix_bwd",
-              launch_mix_bwd(xh, (const float2 *)w_, gyh, gx_ ? gxh : nullptr, (float2 *)gw_, d.B, d.Ci, d.Co,
+              launch_mix_bwd(xh, mix_w(p, w_).w, mix_w(p, w_).q, mix_w(p, w_).scale, gyh, gx_ ? gxh : nullptr,
+                             (float2 *)gw_, d.B, d.Ci, d.Co,
                              d.nmode, accumulate, st));
     if (gx_) {
         inverse_xy(p, gxh, d.Ci, t2, t1, st);
@@ -419,7 +445,8 @@ static int block_bwd_impl(const fno_plan_t *p, const void *x_, const void *cache
                       launch_pw_reduce(part, (float *)gwpw_, (float *)gb_, d.Ci, d.Co, rows_used, accumulate, st));
         forward_spectrum<T>(p, gzt, d.Co, p->tab.wt_inv, t1, t2, gyh, st);
         FNO_TIMED(p, st, "mix_bwd",
-                  launch_mix_bwd(xh, (const float2 *)w_, gyh, gxh, (float2 *)gw_, d.B, d.Ci, d.Co, d.nmode, accumulate,
+                  launch_mix_bwd(xh, mix_w(p, w_).w, mix_w(p, w_).q, mix_w(p, w_).scale, gyh, gxh, (float2 *)gw_, d.B,
+                                 d.Ci, d.Co, d.nmode, accumulate,
                                  st));
         inverse_xy(p, gxh, d.Ci, t2, t1, st);
         FNO_TIMED(p, st, gen ? "zt_adj_tsl" : "zt_adj",
@@ -435,7 +462,8 @@ static int block_bwd_impl(const fno_plan_t *p, const void *x_, const void *cache
     // spectral part: gY^ = (c/N) DFT(gz), then the mix gradients and the adjoint
     forward_spectrum<float>(p, gz, d.Co, p->tab.wt_inv, t1, t2, gyh, st);
     FNO_TIMED(p, st, "mix_bwd",
-              launch_mix_bwd(xh, (const float2 *)w_, gyh, gxh, (float2 *)gw_, d.B, d.Ci, d.Co, d.nmode, accumulate,
+              launch_mix_bwd(xh, mix_w(p, w_).w, mix_w(p, w_).q, mix_w(p, w_).scale, gyh, gxh, (float2 *)gw_, d.B, d.Ci,
+                             d.Co, d.nmode, accumulate,
                              st));
     inverse_xy(p, gxh, d.Ci, t2, t1, st);
     FNO_TIMED(p, st, "inv_zt_adj",
@@ -612,6 +640,27 @@ int fno_cache_bytes(const fno_plan_t *plan, size_t *out)
     if (!plan || !out) return FNO_ERR_INVALID_ARG;
     *out = cache_bytes(plan);
     return FNO_OK;
+}
+
+int fno_packed_weight_bytes(const fno_plan_t *plan, size_t *out)
+{
+    if (!plan || !out) return FNO_ERR_INVALID_ARG;
+    *out = packed_weight_bytes(plan->d.Ci, plan->d.Co, plan->d.nmode);
+    return FNO_OK;
+}
+
+int fno_pack_weights(const fno_plan_t *plan, const void *w, void *wq, size_t wq_bytes, void *stream)
+{
+    int rc = check_plan(plan);
+    if (rc) return rc;
+    if (!w || !wq) return FNO_ERR_INVALID_ARG;
+    if (!aligned16(w) || !aligned16(wq)) return FNO_ERR_ALIGNMENT;
+    const Dims &d = plan->d;
+    if (wq_bytes < packed_weight_bytes(d.Ci, d.Co, d.nmode)) return FNO_ERR_WORKSPACE;
+    hipError_t e = hipSuccess;
+    FNO_TIMED(plan, (hipStream_t)stream, "pack_w_fp8",
+              e = launch_pack_w_fp8((const float2 *)w, wq, d.Ci, d.Co, d.nmode, (hipStream_t)stream));
+    return e == hipSuccess ? FNO_OK : FNO_ERR_HIP;
 }
 
 int fno_spectral_fwd(const fno_plan_t *plan, const void *x, const void *w, void *y, void *cache, void *ws,

@@ -171,4 +171,26 @@ __device__ __forceinline__ float gelu_grad_lgd(float u)
     return fmaf(u * fmaf(-P, P, P), gp, P);
 }
 
+// OCP 8-bit floating point E4M3 (sign, 4 exponent bits with bias 7, 3 mantissa bits; no
+// infinities, S.1111.111 is NaN, largest finite 448, subnormals m 2^-9).
+__device__ __forceinline__ float e4m3_to_f32(unsigned b)
+{
+    const unsigned sgn = (b & 0x80u) << 24, e = (b >> 3) & 15u, m = b & 7u;
+    const float nrm = __uint_as_float(sgn | ((e + 120u) << 23) | (m << 20));   // 2^(e-7) (1 + m/8)
+    const float sub = __uint_as_float(sgn | __float_as_uint((float)m * 0.001953125f));  // m 2^-9
+    return e ? nrm : sub;
+}
+// Nearest E4M3 value, ties to even, magnitudes beyond 448 saturating to 448 (finite inputs).
+__device__ __forceinline__ unsigned f32_to_e4m3(float v)
+{
+    const unsigned sgn = (__float_as_uint(v) >> 24) & 0x80u;
+    const float a = fabsf(v);
+    if (a >= 448.0f) return sgn | 0x7eu;
+    if (a < 0.015625f) return sgn | (unsigned)rintf(a * 512.0f);  // subnormal grid; 8 -> 2^-6, code 0x08
+    unsigned u = __float_as_uint(a);
+    u += 0x7ffffu + ((u >> 20) & 1u);  // round the 23-bit mantissa to 3 bits, ties to even
+    const unsigned r = (((u >> 23) - 120u) << 3) | ((u >> 20) & 7u);
+    return sgn | (r > 0x7eu ? 0x7eu : r);
+}
+
 }  // namespace fno

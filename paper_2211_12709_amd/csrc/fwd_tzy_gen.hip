@@ -29,25 +29,43 @@ TzyArgs tzy_args(const Dims &d, int dtype);
 constexpr int kTzgMaxKB = 3;   // kz blocks of 16 (2 mz <= 48)
 constexpr int kTzgNBW = 4;     // y-step column tiles per wave (Kz Kt <= 16 * 4 * waves)
 
+// Two consecutive values of storage type T as floats (one 4- or 8-byte access, 2-element aligned).
+__device__ __forceinline__ float2 ld_pair_t(const float *p) { return *reinterpret_cast<const float2 *>(p); }
+__device__ __forceinline__ float2 ld_pair_t(const __bf16 *p)
+{
+    const unsigned u = *reinterpret_cast<const unsigned *>(p);
+    return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
+}
+
 // 4 consecutive t of row z starting at t0 (t0 a multiple of 4) as an operand fragment; values at
-// t >= Nt are zero.  VEC: the row start is 4-element aligned (Nt % 4 == 0), so one vector load.
-template <typename T, bool VEC>
+// t >= Nt are zero.  ALN 2: the row start is 4-element aligned (Nt % 4 == 0), one vector load;
+// ALN 1: Nt even, two pair loads; ALN 0: element by element.
+template <typename T, int ALN>
 __device__ __forceinline__ typename OpOf<T>::type load_t4(const T *row, int t0, int Nt)
 {
     typedef typename OpOf<T>::type Op;
-    if (VEC) {
+    if (ALN == 2) {
         if (t0 < Nt) return *reinterpret_cast<const Op *>(row + t0);
         return op_zero<T>();
     }
     float v[4];
+    if (ALN == 1) {
 #pragma unroll
-    for (int j = 0; j < 4; j++) v[j] = t0 + j < Nt ? to_f32(row[t0 + j]) : 0.f;
+        for (int j = 0; j < 4; j += 2) {
+            const float2 f = t0 + j < Nt ? ld_pair_t(row + t0 + j) : make_float2(0.f, 0.f);
+            v[j] = f.x;
+            v[j + 1] = f.y;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; j++) v[j] = t0 + j < Nt ? to_f32(row[t0 + j]) : 0.f;
+    }
     return op_from4<T>(v[0], v[1], v[2], v[3]);
 }
 
 // NTT: n tiles of the t/z steps (1: Kt <= 8; 2: Kt <= 16).  MY: row tiles of the y step.
-// NQM: t chunks of 16 a z block holds (NQ <= NQM).  VEC: Nt % 4 == 0.
-template <typename T, int NTT, bool SPLIT, int MY, int NQM, bool VEC>
+// NQM: t chunks of 16 a z block holds (NQ <= NQM).  ALN: row alignment class (load_t4).
+template <typename T, int NTT, bool SPLIT, int MY, int NQM, int ALN>
 __global__ void __launch_bounds__(64 * FNO_TZYG_NW) __attribute__((amdgpu_waves_per_eu(2)))
 k_tzy_gen(const T *__restrict__ x, float2 *__restrict__ t2, const typename OpOf<T>::type *__restrict__ tabT,
           const typename OpOf<T>::type *__restrict__ tabT_lo, const typename OpOf<T>::type *__restrict__ tabZ,
@@ -96,7 +114,7 @@ k_tzy_gen(const T *__restrict__ x, float2 *__restrict__ t2, const typename OpOf<
         const T *row = xs + ((long long)(ok ? y : 0) * Nz + (ok ? z : 0)) * Nt;
 #pragma unroll
         for (int q = 0; q < NQM; q++)
-            dst[q] = (ok && q < NQ) ? load_t4<T, VEC>(row, 16 * q + 4 * g, Nt) : op_zero<T>();
+            dst[q] = (ok && q < NQ) ? load_t4<T, ALN>(row, 16 * q + 4 * g, Nt) : op_zero<T>();
     };
     __syncthreads();
 
@@ -255,14 +273,14 @@ bool tzy_gen_supported(const Dims &d, int dtype)
     return tzy_gen_lds(a, elem, dtype == FNO_BF16) <= 160 * 1024;
 }
 
-template <typename T, int NTT, int MY, int NQM, bool VEC>
+template <typename T, int NTT, int MY, int NQM, int ALN>
 static hipError_t launch_tzy_gen_t(const T *x, float2 *t2, long long slabs, const TzyTabs &tb, const TzyArgs &a,
                                    hipStream_t st)
 {
     typedef typename OpOf<T>::type Op;
     constexpr bool SPLIT = sizeof(T) == 2;
     const size_t lds = tzy_gen_lds(a, sizeof(T), SPLIT);
-    auto kern = k_tzy_gen<T, NTT, SPLIT, MY, NQM, VEC>;
+    auto kern = k_tzy_gen<T, NTT, SPLIT, MY, NQM, ALN>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -276,15 +294,15 @@ template <typename T, int NTT, int MY>
 static hipError_t launch_tzy_gen_q(const T *x, float2 *t2, long long slabs, const TzyTabs &tb, const TzyArgs &a,
                                    hipStream_t st)
 {
-    const bool vec = a.Nt % 4 == 0;
-    if (a.NQ <= 2)
-        return vec ? launch_tzy_gen_t<T, NTT, MY, 2, true>(x, t2, slabs, tb, a, st)
-                   : launch_tzy_gen_t<T, NTT, MY, 2, false>(x, t2, slabs, tb, a, st);
-    if (a.NQ <= 4)
-        return vec ? launch_tzy_gen_t<T, NTT, MY, 4, true>(x, t2, slabs, tb, a, st)
-                   : launch_tzy_gen_t<T, NTT, MY, 4, false>(x, t2, slabs, tb, a, st);
-    return vec ? launch_tzy_gen_t<T, NTT, MY, 6, true>(x, t2, slabs, tb, a, st)
-               : launch_tzy_gen_t<T, NTT, MY, 6, false>(x, t2, slabs, tb, a, st);
+    const int aln = a.Nt % 4 == 0 ? 2 : a.Nt % 2 == 0 ? 1 : 0;
+#define FNO_TZYG_Q(NQM_)                                                                                          \
+    return aln == 2   ? launch_tzy_gen_t<T, NTT, MY, NQM_, 2>(x, t2, slabs, tb, a, st)                             \
+           : aln == 1 ? launch_tzy_gen_t<T, NTT, MY, NQM_, 1>(x, t2, slabs, tb, a, st)                             \
+                      : launch_tzy_gen_t<T, NTT, MY, NQM_, 0>(x, t2, slabs, tb, a, st)
+    if (a.NQ <= 2) FNO_TZYG_Q(2);
+    if (a.NQ <= 4) FNO_TZYG_Q(4);
+    FNO_TZYG_Q(6);
+#undef FNO_TZYG_Q
 }
 
 template <typename T, int NTT>

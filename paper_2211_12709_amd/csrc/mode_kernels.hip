@@ -104,6 +104,23 @@ __global__ void k_mix_bwd_w(const float2 *__restrict__ xh, const float2 *__restr
     }
 }
 
+// Weight access of the mix kernels: complex64 W, or W packed as two OCP e4m3 bytes per complex
+// value with one power-of-two scale per (i, o) channel pair (fno_pack_weights, fp8.hip).
+struct WComplex {
+    const float2 *w;
+    __device__ __forceinline__ float2 get(long long idx, int) const { return w[idx]; }
+};
+struct WFp8 {
+    const unsigned short *q;
+    const float *scale;
+    __device__ __forceinline__ float2 get(long long idx, int io) const
+    {
+        const unsigned v = q[idx];
+        const float sc = scale[io];
+        return make_float2(e4m3_to_f32(v & 0xffu) * sc, e4m3_to_f32(v >> 8) * sc);
+    }
+};
+
 // Tiled mix: a workgroup owns KM (64 or 32) consecutive retained modes; the batch's X^ (or gY^)
 // of all channels at those modes is staged in LDS once, and the 256 / KM groups of KM lanes split
 // the output channels.  The batch is held in registers (BM >= B), so every W element is read
@@ -111,8 +128,8 @@ __global__ void k_mix_bwd_w(const float2 *__restrict__ xh, const float2 *__restr
 // gY^ are read once.
 
 // Y^[b][o][k] = sum_i X^[b][i][k] W[i][o][k]
-template <int KM, int BM>
-__global__ void __launch_bounds__(256) k_mix_fwd_t(const float2 *__restrict__ xh, const float2 *__restrict__ w,
+template <int KM, int BM, typename WL>
+__global__ void __launch_bounds__(256) k_mix_fwd_t(const float2 *__restrict__ xh, const WL w,
                                                    float2 *__restrict__ yh, int B, int Ci, int Co, long long M)
 {
     constexpr int NG = 256 / KM;
@@ -130,7 +147,7 @@ __global__ void __launch_bounds__(256) k_mix_fwd_t(const float2 *__restrict__ xh
 #pragma unroll
         for (int b = 0; b < BM; b++) re[b] = im[b] = 0.f;
         for (int i = 0; i < Ci; i++) {
-            const float2 q = w[((long long)i * Co + o) * M + k];
+            const float2 q = w.get(((long long)i * Co + o) * M + k, i * Co + o);
 #pragma unroll
             for (int b = 0; b < BM; b++)
                 if (b < B) {
@@ -147,8 +164,8 @@ __global__ void __launch_bounds__(256) k_mix_fwd_t(const float2 *__restrict__ xh
 
 // gX^[b][i][k] = sum_o gY^[b][o][k] conj(W[i][o][k]) and gW[i][o][k] (+)= sum_b conj(X^[b][i][k]) gY^[b][o][k],
 // one pass over W and gW (either output may be null; with gw null, xh may be null).
-template <int KM, int BM>
-__global__ void __launch_bounds__(256) k_mix_bwd_t(const float2 *__restrict__ xh, const float2 *__restrict__ w,
+template <int KM, int BM, typename WL>
+__global__ void __launch_bounds__(256) k_mix_bwd_t(const float2 *__restrict__ xh, const WL w,
                                                    const float2 *__restrict__ gyh, float2 *__restrict__ gxh,
                                                    float2 *__restrict__ gw, int B, int Ci, int Co, long long M,
                                                    int accumulate)
@@ -176,7 +193,7 @@ __global__ void __launch_bounds__(256) k_mix_bwd_t(const float2 *__restrict__ xh
         for (int o = 0; o < Co; o++) {
             const long long wi = ((long long)i * Co + o) * M + k;
             if (gxh) {
-                const float2 q = w[wi];
+                const float2 q = w.get(wi, i * Co + o);
 #pragma unroll
                 for (int b = 0; b < BM; b++)
                     if (b < B) {
@@ -304,34 +321,29 @@ static int mix_tile(int B, int C)
     return 0;
 }
 
-template <int KM>
-static void launch_mix_fwd_km(const float2 *xh, const float2 *w, float2 *yh, int B, int Ci, int Co, long long M,
+// Whether both mix directions run on the tiled kernels (the only ones that read packed weights).
+bool mix_tiled(int B, int Ci, int Co) { return mix_tile(B, Ci) != 0 && mix_tile(B, Co + Ci) != 0; }
+
+template <int KM, typename WL>
+static void launch_mix_fwd_km(const float2 *xh, const WL w, float2 *yh, int B, int Ci, int Co, long long M,
                               hipStream_t st)
 {
     const size_t lds = sizeof(float2) * (size_t)B * Ci * KM;
     const dim3 grid((unsigned)((M + KM - 1) / KM));
-    if (B <= 1) hipLaunchKernelGGL((k_mix_fwd_t<KM, 1>), grid, dim3(256), lds, st, xh, w, yh, B, Ci, Co, M);
-    else if (B <= 2) hipLaunchKernelGGL((k_mix_fwd_t<KM, 2>), grid, dim3(256), lds, st, xh, w, yh, B, Ci, Co, M);
-    else if (B <= 4) hipLaunchKernelGGL((k_mix_fwd_t<KM, 4>), grid, dim3(256), lds, st, xh, w, yh, B, Ci, Co, M);
-    else hipLaunchKernelGGL((k_mix_fwd_t<KM, 8>), grid, dim3(256), lds, st, xh, w, yh, B, Ci, Co, M);
+    if (B <= 1) hipLaunchKernelGGL((k_mix_fwd_t<KM, 1, WL>), grid, dim3(256), lds, st, xh, w, yh, B, Ci, Co, M);
+    else if (B <= 2) hipLaunchKernelGGL((k_mix_fwd_t<KM, 2, WL>), grid, dim3(256), lds, st, xh, w, yh, B, Ci, Co, M);
+    else if (B <= 4) hipLaunchKernelGGL((k_mix_fwd_t<KM, 4, WL>), grid, dim3(256), lds, st, xh, w, yh, B, Ci, Co, M);
+    else hipLaunchKernelGGL((k_mix_fwd_t<KM, 8, WL>), grid, dim3(256), lds, st, xh, w, yh, B, Ci, Co, M);
 }
 
-void launch_mix_fwd(const float2 *xh, const float2 *w, float2 *yh, int B, int Ci, int Co, long long M, hipStream_t st)
-{
-    const int km = mix_tile(B, Ci);
-    if (km == 64) return launch_mix_fwd_km<64>(xh, w, yh, B, Ci, Co, M, st);
-    if (km == 32) return launch_mix_fwd_km<32>(xh, w, yh, B, Ci, Co, M, st);
-    hipLaunchKernelGGL(k_mix_fwd, dim3(grid_for((long long)B * Co * M, 256)), dim3(256), 0, st, xh, w, yh, B, Ci, Co, M);
-}
-
-template <int KM>
-static void launch_mix_bwd_km(const float2 *xh, const float2 *w, const float2 *gyh, float2 *gxh, float2 *gw, int B,
+template <int KM, typename WL>
+static void launch_mix_bwd_km(const float2 *xh, const WL w, const float2 *gyh, float2 *gxh, float2 *gw, int B,
                               int Ci, int Co, long long M, int accumulate, hipStream_t st)
 {
     const size_t lds = sizeof(float2) * (size_t)B * (Co + (gw ? Ci : 0)) * KM;
     const dim3 grid((unsigned)((M + KM - 1) / KM));
 #define FNO_MIX_BWD(BM_)                                                                                         \
-    hipLaunchKernelGGL((k_mix_bwd_t<KM, BM_>), grid, dim3(256), lds, st, xh, w, gyh, gxh, gw, B, Ci, Co, M,     \
+    hipLaunchKernelGGL((k_mix_bwd_t<KM, BM_, WL>), grid, dim3(256), lds, st, xh, w, gyh, gxh, gw, B, Ci, Co, M, \
                        accumulate)
     if (B <= 1) FNO_MIX_BWD(1);
     else if (B <= 2) FNO_MIX_BWD(2);
@@ -340,12 +352,35 @@ static void launch_mix_bwd_km(const float2 *xh, const float2 *w, const float2 *g
 #undef FNO_MIX_BWD
 }
 
-void launch_mix_bwd(const float2 *xh, const float2 *w, const float2 *gyh, float2 *gxh, float2 *gw, int B, int Ci,
-                    int Co, long long M, int accumulate, hipStream_t st)
+// w: complex64 weights, or (wq != null) packed e4m3 weights wq with per-channel-pair scales wscale.
+void launch_mix_fwd(const float2 *xh, const float2 *w, const unsigned short *wq, const float *wscale, float2 *yh,
+                    int B, int Ci, int Co, long long M, hipStream_t st)
+{
+    const int km = mix_tile(B, Ci);
+    if (wq) {
+        const WFp8 wl{wq, wscale};
+        if (km == 64) return launch_mix_fwd_km<64>(xh, wl, yh, B, Ci, Co, M, st);
+        return launch_mix_fwd_km<32>(xh, wl, yh, B, Ci, Co, M, st);  // the plan checked mix_tiled
+    }
+    const WComplex wl{w};
+    if (km == 64) return launch_mix_fwd_km<64>(xh, wl, yh, B, Ci, Co, M, st);
+    if (km == 32) return launch_mix_fwd_km<32>(xh, wl, yh, B, Ci, Co, M, st);
+    hipLaunchKernelGGL(k_mix_fwd, dim3(grid_for((long long)B * Co * M, 256)), dim3(256), 0, st, xh, w, yh, B, Ci, Co, M);
+}
+
+void launch_mix_bwd(const float2 *xh, const float2 *w, const unsigned short *wq, const float *wscale,
+                    const float2 *gyh, float2 *gxh, float2 *gw, int B, int Ci, int Co, long long M, int accumulate,
+                    hipStream_t st)
 {
     const int km = mix_tile(B, Co + (gw ? Ci : 0));
-    if (km == 64) return launch_mix_bwd_km<64>(xh, w, gyh, gxh, gw, B, Ci, Co, M, accumulate, st);
-    if (km == 32) return launch_mix_bwd_km<32>(xh, w, gyh, gxh, gw, B, Ci, Co, M, accumulate, st);
+    if (wq) {
+        const WFp8 wl{wq, wscale};
+        if (km == 64) return launch_mix_bwd_km<64>(xh, wl, gyh, gxh, gw, B, Ci, Co, M, accumulate, st);
+        return launch_mix_bwd_km<32>(xh, wl, gyh, gxh, gw, B, Ci, Co, M, accumulate, st);
+    }
+    const WComplex wl{w};
+    if (km == 64) return launch_mix_bwd_km<64>(xh, wl, gyh, gxh, gw, B, Ci, Co, M, accumulate, st);
+    if (km == 32) return launch_mix_bwd_km<32>(xh, wl, gyh, gxh, gw, B, Ci, Co, M, accumulate, st);
     if (gxh)
         hipLaunchKernelGGL(k_mix_bwd_x, dim3(grid_for((long long)B * Ci * M, 256)), dim3(256), 0, st, gyh, w, gxh, B,
                            Ci, Co, M);

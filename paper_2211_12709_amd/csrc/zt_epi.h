@@ -113,6 +113,7 @@ struct ZtArgs {
     int off_v, off_x;  // LDS byte offsets of the V chunk and the transposed source chunk
     int NS;    // t slices of 16 NTQ values (1 unless the general kernel)
     int al;    // alignment of a lane's t run in memory (general kernel): 2 whole run, 1 runs of 4, 0 none
+    int pr;    // general kernel, al == 0: Nt even, so pairs of t are 2-element aligned
     int accumulate;
 };
 
@@ -197,6 +198,19 @@ __device__ __forceinline__ s4v op_gather(const __bf16 *p, int stride)
 }
 
 template <int EPI> constexpr bool has_src_c() { return EPI != ZEPI_PLAIN; }
+
+// Two consecutive values of storage type T as floats (one 4- or 8-byte access; p 2-element aligned).
+__device__ __forceinline__ float2 ld_pair(const float *p) { return *reinterpret_cast<const float2 *>(p); }
+__device__ __forceinline__ float2 ld_pair(const __bf16 *p)
+{
+    const unsigned u = *reinterpret_cast<const unsigned *>(p);
+    return make_float2(__uint_as_float(u << 16), __uint_as_float(u & 0xffff0000u));
+}
+__device__ __forceinline__ void st_pair(float *p, float a, float b) { *reinterpret_cast<float2 *>(p) = make_float2(a, b); }
+__device__ __forceinline__ void st_pair(__bf16 *p, float a, float b)
+{
+    *reinterpret_cast<unsigned *>(p) = (unsigned)(unsigned short)bf16_bits(a) | ((unsigned)(unsigned short)bf16_bits(b) << 16);
+}
 
 // phase 2 for the current z chunk (and t slice): every tile of this wave.  With AHEAD, group j
 // of this wave has its epilogue operand loaded one z chunk ahead (gi is hidden from the
@@ -396,8 +410,17 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                 e[mt] = *reinterpret_cast<const Op *>(p + 4 * mt);
             } else if (tm < Nt) {
                 float v[4];
+                if (a.pr) {  // Nt and tm even: whole pairs in or out
 #pragma unroll
-                for (int j = 0; j < 4; j++) v[j] = tm + j < Nt ? to_f32(p[4 * mt + j]) : 0.f;
+                    for (int j = 0; j < 4; j += 2) {
+                        const float2 f = tm + j < Nt ? ld_pair(p + 4 * mt + j) : make_float2(0.f, 0.f);
+                        v[j] = f.x;
+                        v[j + 1] = f.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; j++) v[j] = tm + j < Nt ? to_f32(p[4 * mt + j]) : 0.f;
+                }
                 e[mt] = op_from4<T>(v[0], v[1], v[2], v[3]);
             }
         }
@@ -414,6 +437,10 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
             const int tm = t0 + 4 * mt;
             if (a.al >= 1 && tm + 4 <= Nt) {
                 store4(p + 4 * mt, v[mt]);
+            } else if (a.pr) {
+#pragma unroll
+                for (int j = 0; j < 4; j += 2)
+                    if (tm + j < Nt) st_pair(p + 4 * mt + j, v[mt][j], v[mt][j + 1]);
             } else {
 #pragma unroll
                 for (int j = 0; j < 4; j++)
@@ -546,6 +573,16 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                             const bool okc = ok && ci < Csrc;
                             if (a.al >= 1 && tq + 4 <= Nt) {
                                 v[m][k] = okc ? *reinterpret_cast<const Op *>(sp + (long long)ci * ncell) : op_zero<T>();
+                            } else if (a.pr) {
+                                float f[4];
+#pragma unroll
+                                for (int j = 0; j < 4; j += 2) {
+                                    const float2 q = (okc && tq + j < Nt) ? ld_pair(sp + (long long)ci * ncell + j)
+                                                                          : make_float2(0.f, 0.f);
+                                    f[j] = q.x;
+                                    f[j + 1] = q.y;
+                                }
+                                v[m][k] = op_from4<T>(f[0], f[1], f[2], f[3]);
                             } else {
                                 float f[4];
 #pragma unroll
@@ -906,6 +943,7 @@ static size_t zt_layout_zc(const Dims &d, int Cs, int Csrc, int elem, int target
     a.NS = (d.N[3] + 16 * a.NTQ - 1) / (16 * a.NTQ);
     if (elem == 4) a.al = d.N[3] % 4 == 0 ? 2 : 0;
     else a.al = d.N[3] % 8 == 0 ? 2 : d.N[3] % 4 == 0 ? (a.NTQ == 1 ? 2 : 1) : 0;
+    a.pr = d.N[3] % 2 == 0;
     a.ZG = 16 / gcd_int(Cs, 16);
     a.ZC = zc;
     a.NT = a.ZG * Cs / 16;

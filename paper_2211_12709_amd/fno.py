@@ -21,12 +21,13 @@ LIB_PATH = os.path.join(HERE, "libfno_mi355x.so")
 
 FNO_OK, FNO_ERR_INVALID_ARG, FNO_ERR_UNSUPPORTED, FNO_ERR_ALIGNMENT, FNO_ERR_WORKSPACE, FNO_ERR_HIP, FNO_ERR_OOM = range(7)
 FNO_F32, FNO_BF16 = 0, 1
+FNO_W_FP8 = 1
 OP_SPECTRAL_FWD, OP_SPECTRAL_BWD, OP_BLOCK_FWD, OP_BLOCK_BWD = range(4)
 
 EXPORTS = ("fno_desc_validate", "fno_plan_create", "fno_plan_destroy", "fno_workspace_bytes", "fno_cache_bytes",
            "fno_spectral_fwd", "fno_spectral_fwd_noalloc", "fno_spectral_bwd", "fno_block_fwd", "fno_block_bwd",
            "fno_lift_fwd", "fno_lift_bwd", "fno_proj_fwd", "fno_proj_bwd", "fno_mse", "fno_glue_workspace_bytes",
-           "fno_timing_enable", "fno_timing_read", "fno_status_str")
+           "fno_timing_enable", "fno_timing_read", "fno_packed_weight_bytes", "fno_pack_weights", "fno_status_str")
 NOALLOC_SCRATCH_BYTES = 32 << 20  # FNO_NOALLOC_SCRATCH_BYTES
 
 
@@ -75,6 +76,8 @@ def load_library(path: str = LIB_PATH):
     L.fno_glue_workspace_bytes.argtypes = [i32, i32, i32, ctypes.POINTER(_sz)]
     L.fno_timing_enable.argtypes = [_vp, ctypes.c_int]
     L.fno_timing_read.argtypes = [_vp, ctypes.c_char_p, _sz]
+    L.fno_packed_weight_bytes.argtypes = [_vp, ctypes.POINTER(_sz)]
+    L.fno_pack_weights.argtypes = [_vp, _vp, _vp, _sz, _vp]
     L.fno_status_str.argtypes = [ctypes.c_int]
     L.fno_status_str.restype = ctypes.c_char_p
     for f in EXPORTS[:-1]:
@@ -120,9 +123,10 @@ _TORCH_DTYPE = {FNO_F32: torch.float32, FNO_BF16: torch.bfloat16}
 class Plan:
     """A plan for one block shape: basis tables on the current device."""
 
-    def __init__(self, B, C_in, C_out, grid, modes, dtype=FNO_F32):
+    def __init__(self, B, C_in, C_out, grid, modes, dtype=FNO_F32, flags=0):
         L = load_library()
-        self.desc = make_desc(B, C_in, C_out, grid, modes, dtype)
+        self.desc = make_desc(B, C_in, C_out, grid, modes, dtype, flags)
+        self.flags = flags
         self.B, self.C_in, self.C_out = B, C_in, C_out
         self.grid, self.modes, self.dtype = tuple(grid), tuple(modes), dtype
         self.kshape = (2 * modes[0], 2 * modes[1], 2 * modes[2], modes[3])
@@ -161,6 +165,19 @@ class Plan:
             ws = torch.empty(max(n, 256), dtype=torch.uint8, device=self.device)
             self._ws[key] = ws
         return ws
+
+    def packed_weight_bytes(self):
+        n = _sz()
+        _check(_lib.fno_packed_weight_bytes(self._h, ctypes.byref(n)), "fno_packed_weight_bytes")
+        return n.value
+
+    def pack_weights(self, w, out=None):
+        """fno_pack_weights: complex64 weights -> the packed E4M3 form (uint8 tensor) that plans
+        created with FNO_W_FP8 take in place of w."""
+        if out is None:
+            out = torch.empty(self.packed_weight_bytes(), dtype=torch.uint8, device=self.device)
+        _check(_lib.fno_pack_weights(self._h, _ptr(w), _ptr(out), out.numel(), _stream()), "fno_pack_weights")
+        return out
 
     def new_cache(self):
         return torch.empty(self.cache_bytes(), dtype=torch.uint8, device=self.device)

@@ -68,14 +68,21 @@ def test_valid_descriptors(fno, name, dtype):
     (dict(grid=(16, 16, 0, 8)), 1), (dict(modes=(0, 4, 4, 4)), 1),
     (dict(modes=(9, 4, 4, 4)), 1),            # 2 m_x > N_x
     (dict(modes=(4, 4, 4, 6)), 1),            # m_t > N_t/2 + 1
-    (dict(dtype=7), 2), (dict(flags=1), 2),
+    (dict(dtype=7), 2), (dict(flags=2), 2),  # an unknown flag
     (dict(C_in=65), 2),                       # beyond the library's channel limit
+    (dict(B=9, flags=1), 2),                  # packed FP8 weights: the tiled mix holds at most 8 batch elements
 ])
 def test_invalid_descriptors(fno, bad, code):
     args = dict(B=1, C_in=8, C_out=8, grid=(16, 16, 16, 8), modes=(4, 4, 4, 4), dtype=0, flags=0)
     args.update(bad)
     d = fno.make_desc(args["B"], args["C_in"], args["C_out"], args["grid"], args["modes"], args["dtype"], args["flags"])
     assert fno.validate(d) == code
+
+
+@pytest.mark.parametrize("name", sorted(CONFIGS))
+def test_fp8_weight_flag_accepted(fno, name):
+    B, ci, co, grid, modes = CONFIGS[name]
+    assert fno.validate(fno.make_desc(B, ci, co, grid, modes, 1, fno.FNO_W_FP8)) == fno.FNO_OK
 
 
 def test_null_descriptor_and_plan_arguments(fno):
