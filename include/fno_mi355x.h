@@ -186,7 +186,8 @@ int fno_lift_bwd(int32_t dtype, int32_t B, int32_t C_in, int32_t C_out, int64_t 
                  void *stream);
 /* Decoder (Alg. 1, two pointwise layers): y = w2 GELU(w1 x + b1) + b2 with
  * H hidden channels that are never stored; w1 [H][C_in], b1 [H], w2 [C_out][H],
- * b2 [C_out] (biases nullable).  Limits: C_in <= 32, H <= 128, C_out == 1. */
+ * b2 [C_out] (biases nullable).  Limits: C_in <= 32, H <= 128, C_out == 1,
+ * N < 2^31 - 16 (FNO_ERR_UNSUPPORTED otherwise). */
 int fno_proj_fwd(int32_t dtype, int32_t B, int32_t C_in, int32_t H, int32_t C_out, int64_t N, const void *x,
                  const float *w1, const float *b1, const float *w2, const float *b2, void *y, void *stream);
 /* Backward of the decoder: gx (required) and gw1, gb1, gw2, gb2 (nullable).

@@ -21,6 +21,13 @@ FLAGS = [
     "-Wall", "-Wno-unused-result", "-Wno-unknown-pragmas",
 ]
 
+# Per-source additions.  The network glue keeps its matrix-core results in ordinary VGPRs (its
+# accumulators feed VALU math every tile; the accumulator-register form costs a copy per value
+# and, in the decoder's backward, an occupancy step).
+FILE_FLAGS = {
+    "glue.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
 
 def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
@@ -41,7 +48,8 @@ def build(verbose: bool = False, only_changed: bool = False) -> str:
                 os.path.getmtime(obj) > max(os.path.getmtime(src), newest_header):
             objs.append(obj)
             continue
-        cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], "-c", src, "-o", obj,
+        cmd = [HIPCC, *[f for f in FLAGS if f != "-shared"], *FILE_FLAGS.get(os.path.basename(src), []), "-c", src,
+               "-o", obj,
                "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
         objs.append(obj)

@@ -478,6 +478,7 @@ static int block_bwd_impl(const fno_plan_t *p, const void *x_, const void *cache
 namespace fno {
 int glue_blocks();
 size_t proj_part_len(int Ci, int H);
+int proj_part_chunks();
 void launch_sum_rows(const float *part, float *out, int len, size_t stride, int nchunk, int accumulate, hipStream_t st);
 template <typename T>
 hipError_t launch_lift_fwd(const T *x, T *y, const float *w, const float *b, int B, int Ci, int Co, long long N,
@@ -488,14 +489,14 @@ hipError_t launch_lift_bwd(const T *x, const T *gy, const float *w, const float 
 template <typename T>
 hipError_t launch_proj(bool bwd, int B, int Ci, int H, int Co, long long N, const T *x, const T *gy, T *y_or_gx,
                        const float *w1, const float *b1, const float *w2, const float *b2, float *part, int accumulate,
-                       hipStream_t st);
+                       hipStream_t st, int *nchunk);
 template <typename T>
 hipError_t launch_mse(const T *y, const T *t, T *gy, float *part, float *loss, long long n, hipStream_t st);
 
 static size_t glue_ws(int Ci, int H, int Co)
 {
     const size_t lift = (size_t)glue_blocks() * Co * (Ci + 1) * sizeof(float);
-    const size_t proj = (size_t)glue_blocks() * 4 * proj_part_len(Ci, H) * sizeof(float);
+    const size_t proj = (size_t)proj_part_chunks() * proj_part_len(Ci, H) * sizeof(float);
     const size_t mse = (size_t)glue_blocks() * sizeof(float);
     return std::max(std::max(lift, proj), mse);
 }
@@ -791,15 +792,15 @@ int fno_proj_fwd(int32_t dtype, int32_t B, int32_t C_in, int32_t H, int32_t C_ou
 {
     if (B < 1 || C_in < 1 || H < 1 || C_out < 1 || N < 1 || !x || !w1 || !w2 || !y) return FNO_ERR_INVALID_ARG;
     if (dtype != FNO_F32 && dtype != FNO_BF16) return FNO_ERR_UNSUPPORTED;
-    if (C_in > 32 || H > 128 || C_out != 1) return FNO_ERR_UNSUPPORTED;
+    if (C_in > 32 || H > 128 || C_out != 1 || N > (int64_t)INT32_MAX - 16) return FNO_ERR_UNSUPPORTED;
     if (!al16(x) || !al16(w1) || !al16(w2) || !al16(y) || (b1 && !al16(b1)) || (b2 && !al16(b2)))
         return FNO_ERR_ALIGNMENT;
     hipStream_t st = (hipStream_t)stream;
     hipError_t e = dtype == FNO_BF16
                        ? launch_proj<__bf16>(false, B, C_in, H, C_out, N, (const __bf16 *)x, nullptr, (__bf16 *)y, w1,
-                                             b1, w2, b2, nullptr, 0, st)
+                                             b1, w2, b2, nullptr, 0, st, nullptr)
                        : launch_proj<float>(false, B, C_in, H, C_out, N, (const float *)x, nullptr, (float *)y, w1, b1,
-                                            w2, b2, nullptr, 0, st);
+                                            w2, b2, nullptr, 0, st, nullptr);
     return e == hipSuccess ? FNO_OK : FNO_ERR_HIP;
 }
 
@@ -812,21 +813,21 @@ int fno_proj_bwd(int32_t dtype, int32_t B, int32_t C_in, int32_t H, int32_t C_ou
     if (B < 1 || C_in < 1 || H < 1 || C_out < 1 || N < 1 || !x || !w1 || !w2 || !gy || !gx || !ws)
         return FNO_ERR_INVALID_ARG;
     if (dtype != FNO_F32 && dtype != FNO_BF16) return FNO_ERR_UNSUPPORTED;
-    if (C_in > 32 || H > 128 || C_out != 1) return FNO_ERR_UNSUPPORTED;
+    if (C_in > 32 || H > 128 || C_out != 1 || N > (int64_t)INT32_MAX - 16) return FNO_ERR_UNSUPPORTED;
     if (!al16(x) || !al16(w1) || !al16(w2) || !al16(gy) || !al16(gx) || !al16(ws) || (b1 && !al16(b1)) ||
         (gw1 && !al16(gw1)) || (gb1 && !al16(gb1)) || (gw2 && !al16(gw2)) || (gb2 && !al16(gb2)))
         return FNO_ERR_ALIGNMENT;
     if (ws_bytes < glue_ws(C_in, H, C_out)) return FNO_ERR_WORKSPACE;
     hipStream_t st = (hipStream_t)stream;
     float *part = (float *)ws;
+    int nchunk = 0;
     hipError_t e = dtype == FNO_BF16
                        ? launch_proj<__bf16>(true, B, C_in, H, C_out, N, (const __bf16 *)x, (const __bf16 *)gy,
-                                             (__bf16 *)gx, w1, b1, w2, b2, part, accumulate, st)
+                                             (__bf16 *)gx, w1, b1, w2, b2, part, accumulate, st, &nchunk)
                        : launch_proj<float>(true, B, C_in, H, C_out, N, (const float *)x, (const float *)gy,
-                                            (float *)gx, w1, b1, w2, b2, part, accumulate, st);
+                                            (float *)gx, w1, b1, w2, b2, part, accumulate, st, &nchunk);
     if (e != hipSuccess) return FNO_ERR_HIP;
     const size_t row = proj_part_len(C_in, H);
-    const int nchunk = glue_blocks() * 4;
     launch_sum_rows(part, gw1, H * C_in, row, nchunk, accumulate, st);
     launch_sum_rows(part + (size_t)H * C_in, gb1, H, row, nchunk, accumulate, st);
     launch_sum_rows(part + (size_t)H * C_in + H, gw2, H, row, nchunk, accumulate, st);

@@ -47,26 +47,48 @@ __device__ __forceinline__ f4v mma16(s4v a, s4v b, f4v acc)
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
 }
 
+// Two K chunks in one product: acc + a0 b0 + a1 b1.  For bfloat16 one v_mfma_f32_16x16x32_bf16,
+// whose 8 K values per lane are taken as the two chunks' 4 + 4 (a fixed permutation of K shared by
+// A and B, so the sum over K is unchanged); for float the two chunk products.
+typedef short s8v __attribute__((ext_vector_type(8)));
+typedef __bf16 b8v_ __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ f4v mma32(s4v a0, s4v a1, s4v b0, s4v b1, f4v acc)
+{
+    const s8v a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+    const s8v b = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8v_, a), __builtin_bit_cast(b8v_, b), acc, 0, 0,
+                                                   0);
+}
+__device__ __forceinline__ f4v mma32(f4v a0, f4v a1, f4v b0, f4v b1, f4v acc) { return mma16(a1, b1, mma16(a0, b0, acc)); }
+
 __device__ __forceinline__ short bf16_bits(float v) { return __builtin_bit_cast(short, (__bf16)v); }
+
+// Two floats -> two bfloat16 (round to nearest even) in one 32-bit word, a in the low half: one
+// v_cvt_pk_bf16_f32 (converting the halves one at a time leaves a repack per pair).
+typedef float f2v_ __attribute__((ext_vector_type(2)));
+typedef __bf16 b2v_ __attribute__((ext_vector_type(2)));
+typedef unsigned u2v_ __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ unsigned bf16_pack2(float a, float b)
+{
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(f2v_{a, b}, b2v_));
+}
+__device__ __forceinline__ s4v bf16_pack4(float a, float b, float c, float d)
+{
+    return __builtin_bit_cast(s4v, u2v_{bf16_pack2(a, b), bf16_pack2(c, d)});
+}
 
 // Accumulator (4 floats) -> operand fragment of type T.
 template <typename T> __device__ __forceinline__ typename OpOf<T>::type to_op(f4v v);
 template <> __device__ __forceinline__ f4v to_op<float>(f4v v) { return v; }
-template <> __device__ __forceinline__ s4v to_op<__bf16>(f4v v)
-{
-    s4v r;
-    r[0] = bf16_bits(v[0]);
-    r[1] = bf16_bits(v[1]);
-    r[2] = bf16_bits(v[2]);
-    r[3] = bf16_bits(v[3]);
-    return r;
-}
+template <> __device__ __forceinline__ s4v to_op<__bf16>(f4v v) { return bf16_pack4(v[0], v[1], v[2], v[3]); }
 
 template <typename T> __device__ __forceinline__ typename OpOf<T>::type op_zero();
 template <> __device__ __forceinline__ f4v op_zero<float>() { return f4v{0.f, 0.f, 0.f, 0.f}; }
 template <> __device__ __forceinline__ s4v op_zero<__bf16>() { return s4v{0, 0, 0, 0}; }
 
 __device__ __forceinline__ f4v f4_zero() { return f4v{0.f, 0.f, 0.f, 0.f}; }
+__device__ __forceinline__ f4v op_zero_of(f4v) { return f4_zero(); }
+__device__ __forceinline__ s4v op_zero_of(s4v) { return s4v{0, 0, 0, 0}; }
 
 // Value of lane (l & ~15) | ((l + 8) & 15): rotate each row of 16 lanes by 8 (DPP row_ror:8).
 __device__ __forceinline__ float row_ror8(float v)
@@ -94,7 +116,7 @@ template <typename T> __device__ __forceinline__ typename OpOf<T>::type op_from4
 template <> __device__ __forceinline__ f4v op_from4<float>(float a, float b, float c, float d) { return f4v{a, b, c, d}; }
 template <> __device__ __forceinline__ s4v op_from4<__bf16>(float a, float b, float c, float d)
 {
-    return s4v{bf16_bits(a), bf16_bits(b), bf16_bits(c), bf16_bits(d)};
+    return bf16_pack4(a, b, c, d);
 }
 
 // Store element j of a fragment to *p (its storage type, bits unchanged).
@@ -118,7 +140,7 @@ __device__ __forceinline__ void store4(float *p, const float (&v)[4])
 }
 __device__ __forceinline__ void store4(__bf16 *p, const float (&v)[4])
 {
-    *reinterpret_cast<s4v *>(p) = s4v{bf16_bits(v[0]), bf16_bits(v[1]), bf16_bits(v[2]), bf16_bits(v[3])};
+    *reinterpret_cast<s4v *>(p) = bf16_pack4(v[0], v[1], v[2], v[3]);
 }
 
 // 4x4 transpose: r[j] = {v[0][j], v[1][j], v[2][j], v[3][j]} (element j of four fragments).
@@ -134,7 +156,6 @@ __device__ __forceinline__ void op_transpose4(const s4v (&v)[4], s4v (&r)[4])
 }
 
 // 8 consecutive activations <-> two fragments (one 16-byte access for bfloat16, two for float).
-typedef short s8v __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ void load8(const float *p, f4v &a, f4v &b)
 {
     a = *reinterpret_cast<const f4v *>(p);
@@ -153,8 +174,9 @@ __device__ __forceinline__ void store8(float *p, const float (&v)[2][4])
 }
 __device__ __forceinline__ void store8(__bf16 *p, const float (&v)[2][4])
 {
-    *reinterpret_cast<s8v *>(p) = s8v{bf16_bits(v[0][0]), bf16_bits(v[0][1]), bf16_bits(v[0][2]), bf16_bits(v[0][3]),
-                                      bf16_bits(v[1][0]), bf16_bits(v[1][1]), bf16_bits(v[1][2]), bf16_bits(v[1][3])};
+    typedef unsigned u4v_ __attribute__((ext_vector_type(4)));
+    *reinterpret_cast<u4v_ *>(p) = u4v_{bf16_pack2(v[0][0], v[0][1]), bf16_pack2(v[0][2], v[0][3]),
+                                        bf16_pack2(v[1][0], v[1][1]), bf16_pack2(v[1][2], v[1][3])};
 }
 
 }  // namespace fno

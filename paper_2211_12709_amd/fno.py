@@ -334,15 +334,19 @@ def lift_fwd(x, w, b):
     return y
 
 
-def lift_bwd(x, w, b, gy, need_gw=True, need_gb=True):
+def lift_bwd(x, w, b, gy, need_gw=True, need_gb=True, out=None):
+    """(gw, gb) of the encoder; with out = (gw, gb) the gradients are added into those tensors."""
     B, ci = x.shape[:2]
     co = w.shape[0]
-    gw = torch.empty_like(w) if need_gw else None
-    gb = torch.empty((co,), dtype=torch.float32, device=x.device) if need_gb else None
+    if out is not None:
+        gw, gb = out
+    else:
+        gw = torch.empty_like(w) if need_gw else None
+        gb = torch.empty((co,), dtype=torch.float32, device=x.device) if need_gb else None
     ws = _glue_workspace(x.device, ci, 1, co)
     _check(load_library().fno_lift_bwd(_DTYPE_CODE[x.dtype], B, ci, co, _npts(x), _ptr(x), _ptr(w), _ptr(b),
-                                       _ptr(gy), _ptr(gw), _ptr(gb), 0, _ptr(ws), ws.numel(), _stream()),
-           "fno_lift_bwd")
+                                       _ptr(gy), _ptr(gw), _ptr(gb), int(out is not None), _ptr(ws), ws.numel(),
+                                       _stream()), "fno_lift_bwd")
     return gw, gb
 
 
@@ -355,17 +359,23 @@ def proj_fwd(x, w1, b1, w2, b2):
     return y
 
 
-def proj_bwd(x, w1, b1, w2, b2, gy):
+def proj_bwd(x, w1, b1, w2, b2, gy, out=None):
+    """(gx, gw1, gb1, gw2, gb2) of the decoder; with out = those five tensors the gradients are
+    added into them."""
     B, ci = x.shape[:2]
     h, co = w1.shape[0], w2.shape[0]
-    gx = torch.empty_like(x)
-    gw1, gw2 = torch.empty_like(w1), torch.empty_like(w2)
-    gb1 = torch.empty((h,), dtype=torch.float32, device=x.device)
-    gb2 = torch.empty((co,), dtype=torch.float32, device=x.device)
+    if out is not None:
+        gx, gw1, gb1, gw2, gb2 = out
+    else:
+        gx = torch.empty_like(x)
+        gw1, gw2 = torch.empty_like(w1), torch.empty_like(w2)
+        gb1 = torch.empty((h,), dtype=torch.float32, device=x.device)
+        gb2 = torch.empty((co,), dtype=torch.float32, device=x.device)
     ws = _glue_workspace(x.device, ci, h, co)
     _check(load_library().fno_proj_bwd(_DTYPE_CODE[x.dtype], B, ci, h, co, _npts(x), _ptr(x), _ptr(w1), _ptr(b1),
                                        _ptr(w2), _ptr(b2), _ptr(gy), _ptr(gx), _ptr(gw1), _ptr(gb1), _ptr(gw2),
-                                       _ptr(gb2), 0, _ptr(ws), ws.numel(), _stream()), "fno_proj_bwd")
+                                       _ptr(gb2), int(out is not None), _ptr(ws), ws.numel(), _stream()),
+           "fno_proj_bwd")
     return gx, gw1, gb1, gw2, gb2
 
 

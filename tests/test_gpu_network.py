@@ -43,11 +43,17 @@ def dev(a, dtype=torch.float32):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda().to(dtype).contiguous()
 
 
+# (grid, input channels): N = 7680 (vector path), N = 525 (odd length: element path and a
+# ragged last work item), and the CO2 encoder's 3 channels
+LIFT_CASES = {"n7680_c4": ((12, 10, 8, 8), 4), "n525_c4": ((5, 3, 7, 5), 4), "n4608_c3": ((8, 8, 9, 8), 3)}
+
+
 @pytest.mark.parametrize("dt", [torch.float32, torch.bfloat16], ids=["f32", "bf16"])
-def test_lift(fno, o, dt):
-    grid = (12, 10, 8, 8)
-    x = inputs.ns_like_input(2, grid, seed=3)
-    we, be = inputs.linear_weights(20, 4, seed=inputs.SEED_LIFT)
+@pytest.mark.parametrize("case", sorted(LIFT_CASES))
+def test_lift(fno, o, dt, case):
+    grid, ci = LIFT_CASES[case]
+    x = inputs.normal_field((2, ci, *grid), seed=3)
+    we, be = inputs.linear_weights(20, ci, seed=inputs.SEED_LIFT)
     gy = inputs.normal_field((2, 20, *grid), seed=7)
     y = fno.lift_fwd(dev(x, dt), dev(we), dev(be))
     gw, gb = fno.lift_bwd(dev(x, dt), dev(we), dev(be), dev(gy, dt))
@@ -57,23 +63,41 @@ def test_lift(fno, o, dt):
     _, gw_ref, gb_ref = o.lift_bwd(x, we, be, gy)
     assert rel(np64(gw), gw_ref) < tol
     assert rel(np64(gb), gb_ref) < tol
+    # accumulate: a second call adds the same gradients again
+    fno.lift_bwd(dev(x, dt), dev(we), dev(be), dev(gy, dt), out=(gw, gb))
+    torch.cuda.synchronize()
+    assert rel(np64(gw), 2 * gw_ref) < tol
+    assert rel(np64(gb), 2 * gb_ref) < tol
+
+
+# (grid, input channels, hidden channels): the first layer's K chunks (inputs plus the bias row)
+# are 2 for 20 channels, 1 for 8 and 3 for 32; N = 4320 is a whole number of 16-point tiles,
+# N = 525 an odd length (element path, ragged last tile); H = 100 leaves hidden rows unused.
+PROJ_CASES = {"n4320_c20_h128": ((10, 6, 9, 8), 20, 128), "n525_c20_h128": ((5, 3, 7, 5), 20, 128),
+              "n4320_c8_h100": ((10, 6, 9, 8), 8, 100), "n525_c32_h128": ((5, 3, 7, 5), 32, 128)}
 
 
 @pytest.mark.parametrize("dt", [torch.float32, torch.bfloat16], ids=["f32", "bf16"])
-def test_projection(fno, o, dt):
-    grid = (10, 6, 9, 8)
-    x = inputs.normal_field((2, 20, *grid), seed=5)
-    w1, b1 = inputs.linear_weights(128, 20, seed=inputs.SEED_PROJ1)
-    w2, b2 = inputs.linear_weights(1, 128, seed=inputs.SEED_PROJ2)
+@pytest.mark.parametrize("case", sorted(PROJ_CASES))
+def test_projection(fno, o, dt, case):
+    grid, ci, hid = PROJ_CASES[case]
+    x = inputs.normal_field((2, ci, *grid), seed=5)
+    w1, b1 = inputs.linear_weights(hid, ci, seed=inputs.SEED_PROJ1)
+    w2, b2 = inputs.linear_weights(1, hid, seed=inputs.SEED_PROJ2)
     gy = inputs.normal_field((2, 1, *grid), seed=9)
     y = fno.proj_fwd(dev(x, dt), dev(w1), dev(b1), dev(w2), dev(b2))
-    gx, gw1, gb1, gw2, gb2 = fno.proj_bwd(dev(x, dt), dev(w1), dev(b1), dev(w2), dev(b2), dev(gy, dt))
+    outs = fno.proj_bwd(dev(x, dt), dev(w1), dev(b1), dev(w2), dev(b2), dev(gy, dt))
     torch.cuda.synchronize()
     tol = F32_TOL if dt == torch.float32 else BF16_TOL
     assert rel(np64(y), o.proj_fwd(x, w1, b1, w2, b2)) < tol
     refs = o.proj_bwd(x, w1, b1, w2, b2, gy)
-    for name, a, r in zip(("gx", "gw1", "gb1", "gw2", "gb2"), (gx, gw1, gb1, gw2, gb2), refs):
+    for name, a, r in zip(("gx", "gw1", "gb1", "gw2", "gb2"), outs, refs):
         assert rel(np64(a), r) < tol, name
+    # accumulate: a second call adds the same gradients again
+    fno.proj_bwd(dev(x, dt), dev(w1), dev(b1), dev(w2), dev(b2), dev(gy, dt), out=outs)
+    torch.cuda.synchronize()
+    for name, a, r in zip(("gx", "gw1", "gb1", "gw2", "gb2"), outs, refs):
+        assert rel(np64(a), 2 * r) < tol, name + " (accumulated)"
 
 
 def test_mse(fno, o):
