@@ -483,6 +483,8 @@ def main():
     ap.add_argument("--extra-steps", type=int, default=5, help="timed steps of each extra workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--network-only", action="store_true",
+                    help="time only the four-block network step (for profiling it) and print its JSON object")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -491,6 +493,12 @@ def main():
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs as a single process on one GPU.", file=sys.stderr)
         sys.exit(2)
+
+    if args.network_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(run_network_leg(args.extra_steps, 2)), flush=True)
+        return
 
     wl = WORKLOADS[args.workload]
     B, C, grid, modes = wl
