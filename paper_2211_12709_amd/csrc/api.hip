@@ -233,20 +233,27 @@ static int finish()
     return (e == hipSuccess && last == hipSuccess) ? FNO_OK : FNO_ERR_HIP;
 }
 
+#ifndef FNO_AXIS_X_BF16
+#define FNO_AXIS_X_BF16 1  // bfloat16 plans: the x inverse on bfloat16 operands (float results)
+#endif
+
 // X^ of activations `in` (C channels) into xh, using t1/t2 as scratch.
 // One-axis contraction of complex spectra along axis ax (0 = x, 1 = y) on the
 // matrix cores (float operands): in [outer][Nin][cols] -> out [outer][Nout][cols].
 // bf16: bfloat16 operands (spectrum rounded once, basis as a hi + lo pair) with float
 // accumulation, result stored as bfloat16 (re, im) pairs -- used where the consumer
-// rounds it to bfloat16 anyway (the z,t synthesis of the bfloat16 path).
+// rounds it to bfloat16 anyway (the z,t synthesis of the bfloat16 path).  ops16: bfloat16
+// operands the same way, float result (the x inverse of the bfloat16 path, whose output the y
+// inverse rounds to bfloat16 next; the x forward stays float: no faster on bfloat16 operands and
+// it sets the precision of X^ and so of the weight gradient).
 static void axis_stage(const fno_plan_t *p, int ax, bool forward, const float2 *in, float2 *out, long long outer,
-                       long long cols, hipStream_t st, const char *name, bool bf16 = false)
+                       long long cols, hipStream_t st, const char *name, bool bf16 = false, bool ops16 = false)
 {
     const Dims &d = p->d;
     const int Nin = forward ? d.N[ax] : d.K[ax], Nout = forward ? d.K[ax] : d.N[ax];
     const Tables::Frag &tb = forward ? p->tab.ax_fwd[ax] : p->tab.ax_inv[ax];
-    if (bf16 && axis_lds_bytes((Nin + 15) / 16 * 16, 2) <= 160 * 1024) {
-        FNO_TIMED(p, st, name, note(launch_axis_mfma<__bf16>(in, out, tb.hi, tb.lo, outer, Nin, Nout, cols, st, true)));
+    if ((bf16 || ops16) && axis_lds_bytes((Nin + 15) / 16 * 16, 2) <= 160 * 1024) {
+        FNO_TIMED(p, st, name, note(launch_axis_mfma<__bf16>(in, out, tb.hi, tb.lo, outer, Nin, Nout, cols, st, bf16)));
     } else if (axis_lds_bytes((Nin + 15) / 16 * 16, 4) <= 160 * 1024) {
         FNO_TIMED(p, st, name, note(launch_axis_mfma<float>(in, out, tb.f, nullptr, outer, Nin, Nout, cols, st)));
     } else {
@@ -319,7 +326,8 @@ static ZtTabs zt_tabs(const fno_plan_t *p, bool adjoint)
 static void inverse_xy(const fno_plan_t *p, const float2 *spec, int C, float2 *u2, float2 *u1, hipStream_t st)
 {
     const Dims &d = p->d;
-    axis_stage(p, 0, false, spec, u2, (long long)d.B * C, d.P, st, "axis_inv_x");
+    axis_stage(p, 0, false, spec, u2, (long long)d.B * C, d.P, st, "axis_inv_x", false,
+               FNO_AXIS_X_BF16 && p->desc.dtype == FNO_BF16);
     // the y inverse feeds the z,t synthesis, which rounds it to the activation type
     axis_stage(p, 1, false, u2, u1, (long long)d.B * C * d.N[0], d.kplane, st, "axis_inv_y",
                p->desc.dtype == FNO_BF16 && zt_supported(d, FNO_BF16));
