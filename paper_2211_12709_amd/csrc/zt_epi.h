@@ -55,6 +55,12 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3, ZEPI_ADJ_ACC 
 #ifndef FNO_ZT_FILL_ONE
 #define FNO_ZT_FILL_ONE 1  // a workgroup alone on its CU (LDS) takes up to 16 waves
 #endif
+#ifndef FNO_ZT_P1_IM
+#define FNO_ZT_P1_IM 2  // bfloat16 z synthesis without register-resident basis: items per wave at a time
+#endif
+#ifndef FNO_ZT_P1_SPLIT
+#define FNO_ZT_P1_SPLIT 0  // bfloat16 z synthesis with the hi + lo basis (0: hi only)
+#endif
 #ifndef FNO_ZT_GELU_BWD
 #define FNO_ZT_GELU_BWD 1  // bfloat16 BWD GELU': 0 A&S 7.1.26, 1 logistic Phi + exact phi, 2 logistic derivative
 #endif
@@ -612,13 +618,68 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                         const int ti = (zg * a.QZ + q) * 64 + lane, si = ti + QH * 64;
                         tzc[q] = tabZ[ti];
                         tzs[q] = tabZ[si];
-                        if (SPLIT) {
+                        if (SPLIT && FNO_ZT_P1_SPLIT) {
                             tzcl[q] = tabZ_lo[ti];
                             tzsl[q] = tabZ_lo[si];
                         }
                     }
             }
-            for (int item = w; item < Cs * NTT; item += NW) {
+            // without register-resident z basis: IM items of the wave at a time, so that each z-basis
+            // fragment is loaded once for all of them and IM independent product chains wait on it
+            constexpr int IM = sizeof(T) == 2 ? FNO_ZT_P1_IM : 1;
+            if (!tz_reg && IM > 1) {
+                for (int it0 = w; it0 < Cs * NTT; it0 += NW * IM) {
+                    f4v acc[IM];
+                    const T *pcs[IM], *psn[IM];
+                    bool kr[IM], neg[IM];
+#pragma unroll
+                    for (int i = 0; i < IM; i++) {
+                        const int item = it0 + i * NW;
+                        const int cs = NTT == 1 ? item : item >> 1, mt = NTT == 1 ? 0 : item & 1;
+                        const int ri = NTT == 1 ? (c >> 3) : mt;
+                        const int kt = NTT == 1 ? (c & 7) : c;
+                        kr[i] = kt < Kt && item < Cs * NTT;
+                        neg[i] = ri == 0;
+                        const size_t roff = ((size_t)(item < Cs * NTT ? cs : 0) * Kt * Kzp) +
+                                            ((size_t)g * Kt + (kt < Kt ? kt : 0)) * 4;
+                        pcs[i] = (ri == 0 ? ure : uim) + roff;
+                        psn[i] = (ri == 0 ? uim : ure) + roff;
+                        acc[i] = f4_zero();
+                    }
+                    const int qstep = 16 * Kt;
+                    for (int q = 0; q < QH; q++) {
+                        const int ti = (zg * a.QZ + q) * 64 + lane, si = ti + QH * 64;
+                        const Op zcv = tabZ[ti], zsv = tabZ[si];
+                        Op zcl, zsl;
+                        if (SPLIT && FNO_ZT_P1_SPLIT) {
+                            zcl = tabZ_lo[ti];
+                            zsl = tabZ_lo[si];
+                        }
+#pragma unroll
+                        for (int i = 0; i < IM; i++) {
+                            const Op ac = kr[i] ? *reinterpret_cast<const Op *>(pcs[i] + qstep * q) : op_zero<T>();
+                            const Op as =
+                                kr[i] ? op_sign(*reinterpret_cast<const Op *>(psn[i] + qstep * q), neg[i]) : op_zero<T>();
+                            acc[i] = mma16(ac, zcv, acc[i]);
+                            if (SPLIT && FNO_ZT_P1_SPLIT) acc[i] = mma16(ac, zcl, acc[i]);
+                            acc[i] = mma16(as, zsv, acc[i]);
+                            if (SPLIT && FNO_ZT_P1_SPLIT) acc[i] = mma16(as, zsl, acc[i]);
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < IM; i++) {
+                        const int item = it0 + i * NW;
+                        const int cs = NTT == 1 ? item : item >> 1, mt = NTT == 1 ? 0 : item & 1;
+                        const int zc = c - (zc0 & 15);
+                        if (item < Cs * NTT && zc >= 0 && zc < ZC) {
+                            float v[4] = {acc[i][0], acc[i][1], acc[i][2], acc[i][3]};
+                            const int vr = zc * Cs + cs;
+                            store4(vl + (size_t)vr * ldv + 16 * mt + 4 * (g ^ vswz(vr)), v);
+                        }
+                    }
+                }
+            }
+            for (int item = w; item < ((!tz_reg && IM > 1) ? 0 : Cs * NTT); item += NW) {
                 const int cs = NTT == 1 ? item : item >> 1, mt = NTT == 1 ? 0 : item & 1;
                 const int ri = NTT == 1 ? (c >> 3) : mt;
                 const int kt = NTT == 1 ? (c & 7) : c;
@@ -637,9 +698,9 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                             const Op as = krow ? op_sign(*reinterpret_cast<const Op *>(p_sin + qstep * q), ri == 0)
                                                : op_zero<T>();
                             acc = mma16(ac, tzc[q], acc);
-                            if (SPLIT) acc = mma16(ac, tzcl[q], acc);
+                            if (SPLIT && FNO_ZT_P1_SPLIT) acc = mma16(ac, tzcl[q], acc);
                             acc = mma16(as, tzs[q], acc);
-                            if (SPLIT) acc = mma16(as, tzsl[q], acc);
+                            if (SPLIT && FNO_ZT_P1_SPLIT) acc = mma16(as, tzsl[q], acc);
                         }
                 } else {
                     for (int q = 0; q < QH; q++) {
