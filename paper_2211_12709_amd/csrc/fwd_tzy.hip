@@ -30,6 +30,9 @@
 #define FNO_TZY_NW_F32 4  // the same for the float kernel
 #endif
 template <typename T> constexpr int tzy_nw() { return sizeof(T) == 2 ? FNO_TZY_NW_BF16 : FNO_TZY_NW_F32; }
+#ifndef FNO_TZY_TZ_SPLIT
+#define FNO_TZY_TZ_SPLIT 0  // bfloat16: hi + lo basis in the t and z steps (0: hi only; their result is staged in bfloat16)
+#endif
 #ifndef FNO_TZY_WAVES_F32
 #define FNO_TZY_WAVES_F32 1  // the same for the float kernel
 #endif
@@ -73,7 +76,7 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
 #pragma unroll
         for (int nt = 0; nt < NTT; nt++) {
             tb[q][nt] = q < a.NQ ? tabT[(q * NTT + nt) * 64 + lane] : op_zero<T>();
-            if (SPLIT) tbl[q][nt] = q < a.NQ ? tabT_lo[(q * NTT + nt) * 64 + lane] : op_zero<T>();
+            if (SPLIT && FNO_TZY_TZ_SPLIT) tbl[q][nt] = q < a.NQ ? tabT_lo[(q * NTT + nt) * 64 + lane] : op_zero<T>();
         }
 
     f4v acc[NBW][MY];  // y-step tiles: column block w + NW nbi, row block mb (re rows < MY/2 <= im rows)
@@ -126,7 +129,7 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
                         if (q < a.NQ) {
                             c0 = mma16(xa[zb][q], tb[q][nt], c0);
                             c1 = mma16(xb[zb][q], tb[q][nt], c1);
-                            if (SPLIT) {
+                            if (SPLIT && FNO_TZY_TZ_SPLIT) {
                                 c0 = mma16(xa[zb][q], tbl[q][nt], c0);
                                 c1 = mma16(xb[zb][q], tbl[q][nt], c1);
                             }
@@ -140,7 +143,7 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
                         const int ic = (zb * a.MZ + kb) * 64 + lane, is = (zb * a.MZ + a.KB + kb) * 64 + lane;
                         const Op zc = zl[ic], zs = zl[is];
                         Op zcl, zsl;
-                        if (SPLIT) {
+                        if (SPLIT && FNO_TZY_TZ_SPLIT) {
                             zcl = zl[nzf + ic];
                             zsl = zl[nzf + is];
                         }
@@ -150,7 +153,7 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
                             for (int nt = 0; nt < NTT; nt++) {
                                 Pc[u][kb][nt] = mma16(zc, bz[u][nt], Pc[u][kb][nt]);
                                 Ps[u][kb][nt] = mma16(zs, bz[u][nt], Ps[u][kb][nt]);
-                                if (SPLIT) {
+                                if (SPLIT && FNO_TZY_TZ_SPLIT) {
                                     Pc[u][kb][nt] = mma16(zcl, bz[u][nt], Pc[u][kb][nt]);
                                     Ps[u][kb][nt] = mma16(zsl, bz[u][nt], Ps[u][kb][nt]);
                                 }

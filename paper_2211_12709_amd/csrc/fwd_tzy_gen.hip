@@ -22,6 +22,10 @@
 #define FNO_TZYG_NW 8  // waves per workgroup (the y-step tiles are split over them)
 #endif
 
+#ifndef FNO_TZY_TZ_SPLIT
+#define FNO_TZY_TZ_SPLIT 0  // bfloat16: hi + lo basis in the t and z steps (0: hi only; their result is staged in bfloat16)
+#endif
+
 namespace fno {
 
 TzyArgs tzy_args(const Dims &d, int dtype);
@@ -172,7 +176,7 @@ k_tzy_gen(const T *__restrict__ x, float2 *__restrict__ t2, const typename OpOf<
                     if (q < NQ) {
                         const int ti = (q * NTT + nt) * 64 + lane;
                         c1 = mma16(cur[q], tlb[ti], c1);
-                        if (SPLIT) c1 = mma16(cur[q], tlb[ntf + ti], c1);
+                        if (SPLIT && FNO_TZY_TZ_SPLIT) c1 = mma16(cur[q], tlb[ntf + ti], c1);
                     }
                 bz[nt] = to_op<T>(c1);
             }
@@ -187,7 +191,7 @@ k_tzy_gen(const T *__restrict__ x, float2 *__restrict__ t2, const typename OpOf<
                         Pc[kb][nt] = mma16(zc, bz[nt], Pc[kb][nt]);
                         Ps[kb][nt] = mma16(zs, bz[nt], Ps[kb][nt]);
                     }
-                    if (SPLIT) {
+                    if (SPLIT && FNO_TZY_TZ_SPLIT) {
                         const Op zcl = zl[nzf + ic], zsl = zl[nzf + is];
 #pragma unroll
                         for (int nt = 0; nt < NTT; nt++) {

@@ -61,6 +61,9 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3, ZEPI_ADJ_ACC 
 #ifndef FNO_ZT_P1_SPLIT
 #define FNO_ZT_P1_SPLIT 0  // bfloat16 z synthesis with the hi + lo basis (0: hi only)
 #endif
+#ifndef FNO_ZT_P2_SPLIT_BWD
+#define FNO_ZT_P2_SPLIT_BWD 0  // bfloat16 BWD t synthesis with the hi + lo basis (0: hi only; frees its registers)
+#endif
 #ifndef FNO_ZT_GELU_BWD
 #define FNO_ZT_GELU_BWD 1  // bfloat16 BWD GELU': 0 A&S 7.1.26, 1 logistic Phi + exact phi, 2 logistic derivative
 #endif
@@ -329,7 +332,8 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
         wd[s] = op_from4<T>(v[0], v[1], v[2], v[3]);
     }
     const float bj = (bpw && (EPI == ZEPI_BLOCK || EPI == ZEPI_BWD)) ? bpw[co] : 0.f;
-    // t basis (A of the synthesis part)
+    // t basis (A of the synthesis part); the bfloat16 BWD kernel takes it without the lo term
+    constexpr bool P2S = SPLIT && (EPI != ZEPI_BWD || FNO_ZT_P2_SPLIT_BWD);
     Op ta[NTQ][NTT], tal[NTQ][NTT];
     auto load_ta = [&](int ts) {
 #pragma unroll
@@ -338,7 +342,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
             for (int q = 0; q < NTT; q++) {
                 const int ti = ((ts * NTQ + mt) * NTT + q) * 64 + lane;
                 ta[mt][q] = tabT[ti];
-                if (SPLIT) tal[mt][q] = tabT_lo[ti];
+                if (P2S) tal[mt][q] = tabT_lo[ti];
             }
     };
     load_ta(0);
@@ -753,7 +757,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
 #pragma unroll
                     for (int q = 0; q < NTT; q++) {
                         acc[mt] = mma16(ta[mt][q], bv[q], acc[mt]);
-                        if (SPLIT) acc[mt] = mma16(tal[mt][q], bv[q], acc[mt]);
+                        if (P2S) acc[mt] = mma16(tal[mt][q], bv[q], acc[mt]);
                     }
                     if (PW) {
 #pragma unroll
