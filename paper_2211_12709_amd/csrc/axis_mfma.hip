@@ -15,6 +15,13 @@
 #include "fno_internal.h"
 #include "mfma_common.h"
 
+// bfloat16 operands are used for the inverse stages of the bfloat16 path, whose results are
+// rounded to bfloat16 next (stored as bfloat16 pairs, or staged so by the following stage): the
+// basis is then used once (hi only) unless this is set.
+#ifndef FNO_AXIS_BF16_SPLIT
+#define FNO_AXIS_BF16_SPLIT 0
+#endif
+
 namespace fno {
 
 struct AxisArgs {
@@ -61,7 +68,7 @@ __global__ void __launch_bounds__(256) k_axis_mfma(const float2 *__restrict__ in
                                                    const typename OpOf<TC>::type *__restrict__ tab_lo, AxisArgs a)
 {
     typedef typename OpOf<TC>::type Op;
-    constexpr bool SPLIT = sizeof(TC) == 2;
+    constexpr bool SPLIT = sizeof(TC) == 2 && FNO_AXIS_BF16_SPLIT;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), g = lane >> 4, c = lane & 15;
     const long long nchunk = (a.cols + 63) / 64;
@@ -132,7 +139,7 @@ __global__ void __launch_bounds__(256) k_axis_syn(const float2 *__restrict__ in,
                                                   const typename OpOf<TC>::type *__restrict__ tab_lo, AxisArgs a)
 {
     typedef typename OpOf<TC>::type Op;
-    constexpr bool SPLIT = sizeof(TC) == 2;
+    constexpr bool SPLIT = sizeof(TC) == 2 && FNO_AXIS_BF16_SPLIT;
     const int CB = a.CB;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), g = lane >> 4, c = lane & 15;
