@@ -22,6 +22,10 @@
 #define FNO_TZYG_NW 8  // waves per workgroup (the y-step tiles are split over them)
 #endif
 
+#ifndef FNO_TZYG_VEC1
+#define FNO_TZYG_VEC1 1  // bfloat16, even Nt not a multiple of 4: a run of 4 t as one dword-aligned access (else two)
+#endif
+
 #ifndef FNO_TZY_TZ_SPLIT
 #define FNO_TZY_TZ_SPLIT 0  // bfloat16: hi + lo basis in the t and z steps (0: hi only; their result is staged in bfloat16)
 #endif
@@ -54,6 +58,8 @@ __device__ __forceinline__ typename OpOf<T>::type load_t4(const T *row, int t0, 
     }
     float v[4];
     if (ALN == 1) {
+        // Nt even: the run starts on 4 bytes; a whole run is one dword-aligned access
+        if (FNO_TZYG_VEC1 && sizeof(T) == 2 && t0 + 4 <= Nt) return ld_dword_aligned<Op>(row + t0);
 #pragma unroll
         for (int j = 0; j < 4; j += 2) {
             const float2 f = t0 + j < Nt ? ld_pair_t(row + t0 + j) : make_float2(0.f, 0.f);

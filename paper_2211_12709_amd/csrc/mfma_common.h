@@ -143,6 +143,20 @@ __device__ __forceinline__ void store4(__bf16 *p, const float (&v)[4])
     *reinterpret_cast<s4v *>(p) = bf16_pack4(v[0], v[1], v[2], v[3]);
 }
 
+// A fragment (or any vector) from / to global memory that is only 4-byte aligned: a multi-dword
+// access at dword alignment, which the target's global memory model allows (rows of an even
+// number of bfloat16 values start on 4 bytes, not on the vector's own size).
+template <typename V, typename E> __device__ __forceinline__ V ld_dword_aligned(const E *p)
+{
+    V v;
+    __builtin_memcpy(&v, p, sizeof(V));
+    return v;
+}
+template <typename V, typename E> __device__ __forceinline__ void st_dword_aligned(E *p, const V &v)
+{
+    __builtin_memcpy(p, &v, sizeof(V));
+}
+
 // 4x4 transpose: r[j] = {v[0][j], v[1][j], v[2][j], v[3][j]} (element j of four fragments).
 __device__ __forceinline__ void op_transpose4(const f4v (&v)[4], f4v (&r)[4])
 {

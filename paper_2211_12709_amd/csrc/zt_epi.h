@@ -64,6 +64,9 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3, ZEPI_ADJ_ACC 
 #ifndef FNO_ZT_P2_SPLIT_BWD
 #define FNO_ZT_P2_SPLIT_BWD 0  // bfloat16 BWD t synthesis with the hi + lo basis (0: hi only; frees its registers)
 #endif
+#ifndef FNO_ZT_GEN_VEC1
+#define FNO_ZT_GEN_VEC1 1  // t-sliced kernels, even Nt: runs of 4 t as one dword-aligned access (else pairs)
+#endif
 #ifndef FNO_ZT_GELU_BWD
 #define FNO_ZT_GELU_BWD 1  // bfloat16 BWD GELU': 0 A&S 7.1.26, 1 logistic Phi + exact phi, 2 logistic derivative
 #endif
@@ -418,6 +421,8 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
             const int tm = t0 + 4 * mt;
             if (a.al >= 1 && tm + 4 <= Nt) {
                 e[mt] = *reinterpret_cast<const Op *>(p + 4 * mt);
+            } else if (FNO_ZT_GEN_VEC1 && a.pr && tm + 4 <= Nt) {
+                e[mt] = ld_dword_aligned<Op>(p + 4 * mt);  // Nt even: the run starts on 4 bytes
             } else if (tm < Nt) {
                 float v[4];
                 if (a.pr) {  // Nt and tm even: whole pairs in or out
@@ -447,6 +452,8 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
             const int tm = t0 + 4 * mt;
             if (a.al >= 1 && tm + 4 <= Nt) {
                 store4(p + 4 * mt, v[mt]);
+            } else if (FNO_ZT_GEN_VEC1 && a.pr && tm + 4 <= Nt) {
+                st_dword_aligned(p + 4 * mt, op_from4<T>(v[mt][0], v[mt][1], v[mt][2], v[mt][3]));
             } else if (a.pr) {
 #pragma unroll
                 for (int j = 0; j < 4; j += 2)
@@ -583,6 +590,8 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                             const bool okc = ok && ci < Csrc;
                             if (a.al >= 1 && tq + 4 <= Nt) {
                                 v[m][k] = okc ? *reinterpret_cast<const Op *>(sp + (long long)ci * ncell) : op_zero<T>();
+                            } else if (FNO_ZT_GEN_VEC1 && a.pr && tq + 4 <= Nt) {
+                                v[m][k] = okc ? ld_dword_aligned<Op>(sp + (long long)ci * ncell) : op_zero<T>();
                             } else if (a.pr) {
                                 float f[4];
 #pragma unroll
