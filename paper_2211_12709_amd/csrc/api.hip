@@ -46,9 +46,6 @@ void launch_bwd_gz(const float2 *u, const T *x, const T *gy, float *gz, const Di
                    const float *wpw, const float *bpw, hipStream_t st);
 size_t fwd_tz_lds(const Dims &d);
 struct TabGeom;
-struct TzyTabs {
-    const void *t, *t_lo, *z, *z_lo, *y, *y_lo;
-};
 bool tzy_supported(const Dims &d, int dtype);
 bool tzy_gen_supported(const Dims &d, int dtype);
 template <typename T>

@@ -54,6 +54,10 @@ struct TzyArgs {
     int Ny, Nz, Nt, Ky, Kz, Kt;
     int NQ, NZB, KB, MZ, MY, Yc, QY, NYC;
 };
+// Basis tables of the forward t, z, y kernels (fragment order; lo: the bfloat16 hi + lo split).
+struct TzyTabs {
+    const void *t, *t_lo, *z, *z_lo, *y, *y_lo;
+};
 
 }  // namespace fno
 

@@ -59,16 +59,18 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
     const int Ny = a.Ny, Nz = a.Nz, Nt = a.Nt, Kz = a.Kz, Kt = a.Kt;
     const T *xs = x + slab * (long long)Ny * Nz * Nt;
 
-    // LDS: z-basis fragments (hi [+ lo]) then the T1 chunk [col][k] with row stride ldk.
+    // LDS: z-basis fragments (hi [+ lo where the z step uses it]) then the T1 chunk [col][k] with
+    // row stride ldk.
+    constexpr bool TS = SPLIT && FNO_TZY_TZ_SPLIT;
     const int nzf = a.NZB * a.MZ * 64;
     Op *zl = reinterpret_cast<Op *>(smem);
-    T *tl = reinterpret_cast<T *>(smem + sizeof(Op) * nzf * (SPLIT ? 2 : 1));
+    T *tl = reinterpret_cast<T *>(smem + sizeof(Op) * nzf * (TS ? 2 : 1));
     const int ldk = 2 * a.Yc + 4;
     const int ncol = Kz * Kt;
     constexpr int NW = tzy_nw<T>();
     for (int i = threadIdx.x; i < nzf; i += 64 * NW) {
         zl[i] = tabZ[i];
-        if (SPLIT) zl[nzf + i] = tabZ_lo[i];
+        if (TS) zl[nzf + i] = tabZ_lo[i];
     }
     Op tb[2][NTT], tbl[2][NTT];
 #pragma unroll
@@ -263,13 +265,10 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
 }
 
 // ---------------------------------------------------------------- launcher
-struct TzyTabs {
-    const void *t, *t_lo, *z, *z_lo, *y, *y_lo;
-};
 
 size_t tzy_lds_bytes(const TzyArgs &a, int elem, bool split)
 {
-    const size_t zf = (size_t)a.NZB * a.MZ * 64 * 4 * elem * (split ? 2 : 1);
+    const size_t zf = (size_t)a.NZB * a.MZ * 64 * 4 * elem * ((split && FNO_TZY_TZ_SPLIT) ? 2 : 1);
     const size_t tl = (size_t)a.Kz * a.Kt * (2 * a.Yc + 4) * elem;
     return zf + tl;
 }

@@ -22,6 +22,12 @@
 #define FNO_TZYG_NW 8  // waves per workgroup (the y-step tiles are split over them)
 #endif
 
+#ifndef FNO_TZYG_PD_SHORT
+#define FNO_TZYG_PD_SHORT 2  // z blocks in flight per wave when a row has at most 2 t chunks
+#endif
+#ifndef FNO_TZYG_PD_LONG
+#define FNO_TZYG_PD_LONG 2  // the same for longer rows
+#endif
 #ifndef FNO_TZYG_VEC1
 #define FNO_TZYG_VEC1 1  // bfloat16, even Nt not a multiple of 4: a run of 4 t as one dword-aligned access (else two)
 #endif
@@ -92,19 +98,21 @@ k_tzy_gen(const T *__restrict__ x, float2 *__restrict__ t2, const typename OpOf<
 
     // LDS: z-basis fragments [zb][mb] (hi, then lo), t-basis fragments [q][nt] (hi, then lo),
     // then the T1 chunk [col][k] with row stride ldk
+    // (the lo halves only where the t and z steps use them)
+    constexpr bool TS = SPLIT && FNO_TZY_TZ_SPLIT;
     const int nzf = NZB * a.MZ * 64, ntf = NQ * NTT * 64;
     Op *zl = reinterpret_cast<Op *>(smem);
-    Op *tlb = zl + nzf * (SPLIT ? 2 : 1);
-    T *tl = reinterpret_cast<T *>(tlb + ntf * (SPLIT ? 2 : 1));
+    Op *tlb = zl + nzf * (TS ? 2 : 1);
+    T *tl = reinterpret_cast<T *>(tlb + ntf * (TS ? 2 : 1));
     const int ldk = 2 * a.Yc + 4;
     const int ncol = Kz * Kt;
     for (int i = threadIdx.x; i < nzf; i += 64 * NW) {
         zl[i] = tabZ[i];
-        if (SPLIT) zl[nzf + i] = tabZ_lo[i];
+        if (TS) zl[nzf + i] = tabZ_lo[i];
     }
     for (int i = threadIdx.x; i < ntf; i += 64 * NW) {
         tlb[i] = tabT[i];
-        if (SPLIT) tlb[ntf + i] = tabT_lo[i];
+        if (TS) tlb[ntf + i] = tabT_lo[i];
     }
 
     f4v acc[kTzgNBW][MY];  // y-step tiles: column block w + NW nbi, row block mb
@@ -159,8 +167,19 @@ k_tzy_gen(const T *__restrict__ x, float2 *__restrict__ t2, const typename OpOf<
         __syncthreads();
     };
 
-    Op cur[NQM], nxt[NQM];
-    load_zb(plane_y(0), 0, cur);
+    // z blocks in flight per wave: PD (a ring shifted by one block per step, so that every index is
+    // static); few t chunks per row leave room for more
+    constexpr int PD = NQM <= 2 ? FNO_TZYG_PD_SHORT : FNO_TZYG_PD_LONG;
+    const int nblk = nplanes * NZB;
+    auto load_blk = [&](int L, Op (&dst)[NQM]) {
+        if (L < nblk) {
+            const int sp = L / NZB;
+            load_zb(plane_y(sp), L - sp * NZB, dst);
+        }
+    };
+    Op ring[PD][NQM], cur[NQM];
+#pragma unroll
+    for (int k = 0; k < PD; k++) load_blk(k, ring[k]);
     for (int s = 0; s < nplanes; s++) {
         const int y = plane_y(s);
         f4v Pc[kTzgMaxKB][NTT], Ps[kTzgMaxKB][NTT];
@@ -169,9 +188,14 @@ k_tzy_gen(const T *__restrict__ x, float2 *__restrict__ t2, const typename OpOf<
 #pragma unroll
             for (int nt = 0; nt < NTT; nt++) Pc[kb][nt] = Ps[kb][nt] = f4_zero();
         for (int zb = 0; zb < NZB; zb++) {
-            // the next z block (or the next plane's first) is loaded while this one is multiplied
-            if (zb + 1 < NZB) load_zb(y, zb + 1, nxt);
-            else if (s + 1 < nplanes) load_zb(plane_y(s + 1), 0, nxt);
+            // this block leaves the ring; the block PD steps ahead (across planes) enters it
+#pragma unroll
+            for (int q = 0; q < NQM; q++) cur[q] = ring[0][q];
+#pragma unroll
+            for (int k = 0; k + 1 < PD; k++)
+#pragma unroll
+                for (int q = 0; q < NQM; q++) ring[k][q] = ring[k + 1][q];
+            load_blk(s * NZB + zb + PD, ring[PD - 1]);
             // t step: C1 tile of this z block, as the z step's B operand
             Op bz[NTT];
 #pragma unroll
@@ -182,7 +206,7 @@ k_tzy_gen(const T *__restrict__ x, float2 *__restrict__ t2, const typename OpOf<
                     if (q < NQ) {
                         const int ti = (q * NTT + nt) * 64 + lane;
                         c1 = mma16(cur[q], tlb[ti], c1);
-                        if (SPLIT && FNO_TZY_TZ_SPLIT) c1 = mma16(cur[q], tlb[ntf + ti], c1);
+                        if (TS) c1 = mma16(cur[q], tlb[ntf + ti], c1);
                     }
                 bz[nt] = to_op<T>(c1);
             }
@@ -197,7 +221,7 @@ k_tzy_gen(const T *__restrict__ x, float2 *__restrict__ t2, const typename OpOf<
                         Pc[kb][nt] = mma16(zc, bz[nt], Pc[kb][nt]);
                         Ps[kb][nt] = mma16(zs, bz[nt], Ps[kb][nt]);
                     }
-                    if (SPLIT && FNO_TZY_TZ_SPLIT) {
+                    if (TS) {
                         const Op zcl = zl[nzf + ic], zsl = zl[nzf + is];
 #pragma unroll
                         for (int nt = 0; nt < NTT; nt++) {
@@ -206,8 +230,6 @@ k_tzy_gen(const T *__restrict__ x, float2 *__restrict__ t2, const typename OpOf<
                         }
                     }
                 }
-#pragma unroll
-            for (int q = 0; q < NQM; q++) cur[q] = nxt[q];
         }
         // combine the cos/sin halves into the complex spectrum and stage it in LDS
         const int yl = (s % per_wave) * NW + w;
@@ -262,13 +284,11 @@ k_tzy_gen(const T *__restrict__ x, float2 *__restrict__ t2, const typename OpOf<
 }
 
 // ---------------------------------------------------------------- launcher
-struct TzyTabs {
-    const void *t, *t_lo, *z, *z_lo, *y, *y_lo;
-};
 
 static size_t tzy_gen_lds(const TzyArgs &a, int elem, bool split)
 {
-    const size_t op = 4 * (size_t)elem * (split ? 2 : 1);  // bytes of one fragment entry (hi + lo)
+    // bytes of one fragment entry (hi, and lo where the t and z steps use it)
+    const size_t op = 4 * (size_t)elem * ((split && FNO_TZY_TZ_SPLIT) ? 2 : 1);
     return (size_t)a.NZB * a.MZ * 64 * op + (size_t)a.NQ * (a.Kt <= 8 ? 1 : 2) * 64 * op +
            (size_t)a.Kz * a.Kt * (2 * a.Yc + 4) * elem;
 }
