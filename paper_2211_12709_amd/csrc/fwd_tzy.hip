@@ -30,6 +30,9 @@
 #define FNO_TZY_NW_F32 4  // the same for the float kernel
 #endif
 template <typename T> constexpr int tzy_nw() { return sizeof(T) == 2 ? FNO_TZY_NW_BF16 : FNO_TZY_NW_F32; }
+#ifndef FNO_TZY_USE
+#define FNO_TZY_USE 1  // dtypes that take this kernel where it applies (bit 0 bfloat16, bit 1 float; else the general one)
+#endif
 #ifndef FNO_TZY_TZ_SPLIT
 #define FNO_TZY_TZ_SPLIT 0  // bfloat16: hi + lo basis in the t and z steps (0: hi only; their result is staged in bfloat16)
 #endif
@@ -301,6 +304,7 @@ static void tzy_tiles(const Dims &d, int nw, int &MY, int &NBW)
 // Whether the MFMA path covers these dimensions.
 bool tzy_supported(const Dims &d, int dtype)
 {
+    if ((FNO_TZY_USE & (dtype == FNO_BF16 ? 1 : 2)) == 0) return false;
     const int Nt = d.N[3], Nz = d.N[2];
     if (Nt % 4 != 0 || Nt > 32 || Nz > 128 || d.K[3] > 16 || d.K[2] > 32) return false;
     int MY, NBW;
