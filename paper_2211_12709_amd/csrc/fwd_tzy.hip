@@ -13,7 +13,10 @@
 // T1 of Yc planes is staged in LDS, then
 //   y step:  T2[(re/im, ky)][(kz, kt)] += sum_(re/im', y) Ay[..][..] T1[(re/im', y)][(kz, kt)]
 // with Ay = [[cos, sin], [-sin, cos]] of exp(-i theta_y), accumulated in
-// registers over all chunks of y.
+// registers over all chunks of y.  A wave transforms two planes at a time;
+// the bfloat16 variants with room keep the first plane of the current pair in
+// a per-wave LDS slot (workgroups are one per CU by registers, so LDS is free)
+// and have the next pair's loads in flight during the whole pair transform.
 #include "fno_internal.h"
 #include "mfma_common.h"
 
@@ -30,6 +33,9 @@
 #define FNO_TZY_NW_F32 4  // the same for the float kernel
 #endif
 template <typename T> constexpr int tzy_nw() { return sizeof(T) == 2 ? FNO_TZY_NW_BF16 : FNO_TZY_NW_F32; }
+#ifndef FNO_TZY_LDS_RING
+#define FNO_TZY_LDS_RING 1  // bfloat16: one plane of each wave's current pair in LDS, the next pair's loads in flight
+#endif
 #ifndef FNO_TZY_USE
 #define FNO_TZY_USE 1  // dtypes that take this kernel where it applies (bit 0 bfloat16, bit 1 float; else the general one)
 #endif
@@ -42,6 +48,15 @@ template <typename T> constexpr int tzy_nw() { return sizeof(T) == 2 ? FNO_TZY_N
 
 namespace fno {
 
+
+// Byte offset of the plane slots in LDS: after the z-basis fragments and the T1 chunk (16-aligned).
+__host__ __device__ constexpr int tzy_ring_offset(int zbytes, int tbytes) { return (zbytes + tbytes + 15) / 16 * 16; }
+// Whether a kernel variant keeps plane slots in LDS: bfloat16 with one t/z tile and at most 8 y-step
+// accumulator tiles per wave (the others have no registers for the second plane's copy).
+__host__ __device__ constexpr bool tzy_ring(int elem, int ntt, int my, int nbw)
+{
+    return elem == 2 && FNO_TZY_LDS_RING && ntt == 1 && my * nbw <= 8;
+}
 
 // NTT: N tiles of the t/z steps (1: Kt <= 8, re|im in one tile; 2: Kt <= 16).
 // MY: row tiles of the y step (2 ceil(Ky/16)); NBW: its column tiles per wave.
@@ -64,13 +79,18 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
 
     // LDS: z-basis fragments (hi [+ lo where the z step uses it]) then the T1 chunk [col][k] with
     // row stride ldk.
+    // RING: then each wave's slot for the first plane of its current pair, [z block][t chunk][lane].
     constexpr bool TS = SPLIT && FNO_TZY_TZ_SPLIT;
+    constexpr bool RING = tzy_ring(sizeof(T), NTT, MY, NBW);
     const int nzf = a.NZB * a.MZ * 64;
     Op *zl = reinterpret_cast<Op *>(smem);
     T *tl = reinterpret_cast<T *>(smem + sizeof(Op) * nzf * (TS ? 2 : 1));
     const int ldk = 2 * a.Yc + 4;
     const int ncol = Kz * Kt;
     constexpr int NW = tzy_nw<T>();
+    Op *ring = reinterpret_cast<Op *>(smem + tzy_ring_offset(nzf * (TS ? 2 : 1) * (int)sizeof(Op),
+                                                             Kz * Kt * ldk * (int)sizeof(T))) +
+               (size_t)w * a.NZB * 2 * 64;
     for (int i = threadIdx.x; i < nzf; i += 64 * NW) {
         zl[i] = tabZ[i];
         if (TS) zl[nzf + i] = tabZ_lo[i];
@@ -112,7 +132,8 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
     // t and z steps of two planes (s, s + 1) at once: every z-basis fragment read
     // from LDS feeds both planes, and the two independent MFMA chains overlap.
     // Planes beyond Ny have zero input (guarded loads), hence a zero spectrum.
-    auto do_pair = [&](int s, const Op (&xa)[NZBM][2], const Op (&xb)[NZBM][2]) {
+    // fx(u, zb, q): fragment [zb][q] of plane s + u
+    auto do_pair = [&](int s, auto &&fx) {
         // keep the LDS basis reads inside the plane loop (no hoisting into registers)
         asm volatile("" ::: "memory");
         f4v Pc[2][MAXKB][NTT], Ps[2][MAXKB][NTT];  // [plane][kz block][n tile]: cos rows, sin rows
@@ -132,11 +153,12 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
 #pragma unroll
                     for (int q = 0; q < 2; q++)
                         if (q < a.NQ) {
-                            c0 = mma16(xa[zb][q], tb[q][nt], c0);
-                            c1 = mma16(xb[zb][q], tb[q][nt], c1);
+                            const Op xa = fx(0, zb, q), xb = fx(1, zb, q);
+                            c0 = mma16(xa, tb[q][nt], c0);
+                            c1 = mma16(xb, tb[q][nt], c1);
                             if (SPLIT && FNO_TZY_TZ_SPLIT) {
-                                c0 = mma16(xa[zb][q], tbl[q][nt], c0);
-                                c1 = mma16(xb[zb][q], tbl[q][nt], c1);
+                                c0 = mma16(xa, tbl[q][nt], c0);
+                                c1 = mma16(xb, tbl[q][nt], c1);
                             }
                         }
                     bz[0][nt] = to_op<T>(c0);
@@ -233,19 +255,46 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
         }
     };
 
-    // rotating register buffers: DEPTH planes are in flight while a pair is processed
-    constexpr int DEPTH = FNO_TZY_DEPTH;
-    Op xb[DEPTH][NZBM][2];
+    if constexpr (RING) {
+        // the first plane of the loaded pair goes to this wave's LDS slot (each lane reads back
+        // only what it wrote, so no barrier), the second stays in registers, and the next pair's
+        // loads are issued at once: they have the whole transform of this pair to arrive
+        Op xr[2][NZBM][2];
+        load_plane(plane_y(0), xr[0]);
+        load_plane(plane_y(1), xr[1]);
+        for (int s = 0; s < nplanes; s += 2) {  // nplanes is even
 #pragma unroll
-    for (int k = 0; k < DEPTH; k++) load_plane(plane_y(k), xb[k]);
-    for (int s0 = 0; s0 < nplanes; s0 += DEPTH) {  // nplanes is a multiple of DEPTH
+            for (int zb = 0; zb < NZBM; zb++)
+                if (zb < a.NZB)
 #pragma unroll
-        for (int k = 0; k < DEPTH; k += 2) {
-            const int s = s0 + k;
-            do_pair(s, xb[k], xb[k + 1]);
+                    for (int q = 0; q < 2; q++) ring[(zb * 2 + q) * 64 + lane] = xr[0][zb][q];
+            Op x2[NZBM][2];
+#pragma unroll
+            for (int zb = 0; zb < NZBM; zb++)
+#pragma unroll
+                for (int q = 0; q < 2; q++) x2[zb][q] = xr[1][zb][q];
+            if (s + 2 < nplanes) {
+                load_plane(plane_y(s + 2), xr[0]);
+                load_plane(plane_y(s + 3), xr[1]);
+            }
+            do_pair(s, [&](int u, int zb, int q) { return u == 0 ? ring[(zb * 2 + q) * 64 + lane] : x2[zb][q]; });
             chunk_end(s + 1);
-            if (s + DEPTH < nplanes) load_plane(plane_y(s + DEPTH), xb[k]);
-            if (s + 1 + DEPTH < nplanes) load_plane(plane_y(s + 1 + DEPTH), xb[k + 1]);
+        }
+    } else {
+        // rotating register buffers: DEPTH planes are in flight while a pair is processed
+        constexpr int DEPTH = FNO_TZY_DEPTH;
+        Op xb[DEPTH][NZBM][2];
+#pragma unroll
+        for (int k = 0; k < DEPTH; k++) load_plane(plane_y(k), xb[k]);
+        for (int s0 = 0; s0 < nplanes; s0 += DEPTH) {  // nplanes is a multiple of DEPTH
+#pragma unroll
+            for (int k = 0; k < DEPTH; k += 2) {
+                const int s = s0 + k;
+                do_pair(s, [&](int u, int zb, int q) { return xb[k + u][zb][q]; });
+                chunk_end(s + 1);
+                if (s + DEPTH < nplanes) load_plane(plane_y(s + DEPTH), xb[k]);
+                if (s + 1 + DEPTH < nplanes) load_plane(plane_y(s + 1 + DEPTH), xb[k + 1]);
+            }
         }
     }
 
@@ -269,10 +318,12 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
 
 // ---------------------------------------------------------------- launcher
 
-size_t tzy_lds_bytes(const TzyArgs &a, int elem, bool split)
+size_t tzy_lds_bytes(const TzyArgs &a, int elem, bool split, int my, int nbw)
 {
     const size_t zf = (size_t)a.NZB * a.MZ * 64 * 4 * elem * ((split && FNO_TZY_TZ_SPLIT) ? 2 : 1);
     const size_t tl = (size_t)a.Kz * a.Kt * (2 * a.Yc + 4) * elem;
+    if (tzy_ring(elem, a.Kt <= 8 ? 1 : 2, my, nbw))  // the waves' plane slots
+        return (size_t)tzy_ring_offset((int)zf, (int)tl) + (size_t)FNO_TZY_NW_BF16 * a.NZB * 2 * 64 * 4 * elem;
     return zf + tl;
 }
 
@@ -282,7 +333,7 @@ static hipError_t launch_tzy_t(const T *x, float2 *t2, long long slabs, const Tz
 {
     typedef typename OpOf<T>::type Op;
     constexpr bool SPLIT = sizeof(T) == 2;  // bfloat16 kernels use the hi/lo basis
-    const size_t lds = tzy_lds_bytes(a, sizeof(T), SPLIT);
+    const size_t lds = tzy_lds_bytes(a, sizeof(T), SPLIT, MY, NBW);
     auto kern = k_tzy_fwd<T, NTT, SPLIT, MY, NBW, 8, 2>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -316,7 +367,8 @@ bool tzy_supported(const Dims &d, int dtype)
     a.Kz = d.K[2];
     a.Kt = d.K[3];
     a.Yc = dtype == FNO_BF16 ? 32 : 16;
-    return tzy_lds_bytes(a, dtype == FNO_BF16 ? 2 : 4, dtype == FNO_BF16) <= 160 * 1024;
+    const int nbw_t = NBW <= 2 ? 2 : NBW <= 4 ? 4 : 8;  // the instantiated column tiles per wave
+    return tzy_lds_bytes(a, dtype == FNO_BF16 ? 2 : 4, dtype == FNO_BF16, MY, nbw_t) <= 160 * 1024;
 }
 
 TzyArgs tzy_args(const Dims &d, int dtype)
