@@ -88,9 +88,18 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
     const int ldk = 2 * a.Yc + 4;
     const int ncol = Kz * Kt;
     constexpr int NW = tzy_nw<T>();
-    Op *ring = reinterpret_cast<Op *>(smem + tzy_ring_offset(nzf * (TS ? 2 : 1) * (int)sizeof(Op),
-                                                             Kz * Kt * ldk * (int)sizeof(T))) +
-               (size_t)w * a.NZB * 2 * 64;
+    Op *ring0 = reinterpret_cast<Op *>(smem + tzy_ring_offset(nzf * (TS ? 2 : 1) * (int)sizeof(Op),
+                                                              Kz * Kt * ldk * (int)sizeof(T)));
+    Op *ring = ring0 + (size_t)w * a.NZB * 2 * 64;
+    // RING: then two buffers of one chunk's y-basis fragments [hi, lo][K chunk][row tile][lane], the
+    // next chunk's loaded one chunk ahead (no global load in the loop but the planes')
+    const int nyc1 = a.QY * MY * 64;  // fragments of one chunk (hi or lo)
+    Op *ybuf = ring0 + (size_t)NW * a.NZB * 2 * 64;
+    if (RING)
+        for (int i = threadIdx.x; i < nyc1; i += 64 * NW) {
+            ybuf[i] = tabY[i];
+            ybuf[nyc1 + i] = tabY_lo[i];
+        }
     for (int i = threadIdx.x; i < nzf; i += 64 * NW) {
         zl[i] = tabZ[i];
         if (TS) zl[nzf + i] = tabZ_lo[i];
@@ -232,9 +241,15 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
                 Op ay[MY], ayl[MY];
 #pragma unroll
                 for (int mb = 0; mb < MY; mb++) {
-                    const int ti = ((ych * a.QY + q) * MY + mb) * 64 + lane;
-                    ay[mb] = tabY[ti];
-                    if (SPLIT) ayl[mb] = tabY_lo[ti];
+                    if (RING) {
+                        const Op *yb = ybuf + (size_t)(ych & 1) * 2 * nyc1 + (q * MY + mb) * 64 + lane;
+                        ay[mb] = yb[0];
+                        ayl[mb] = yb[nyc1];
+                    } else {
+                        const int ti = ((ych * a.QY + q) * MY + mb) * 64 + lane;
+                        ay[mb] = tabY[ti];
+                        if (SPLIT) ayl[mb] = tabY_lo[ti];
+                    }
                 }
 #pragma unroll
                 for (int nbi = 0; nbi < NBW; nbi++) {
@@ -259,15 +274,39 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
         // the first plane of the loaded pair goes to this wave's LDS slot (each lane reads back
         // only what it wrote, so no barrier), the second stays in registers, and the next pair's
         // loads are issued at once: they have the whole transform of this pair to arrive
+        // The next chunk's y-basis fragments (this wave's share) are requested at a chunk's first
+        // pair, before that pair's plane loads, and stored at its last pair, once those planes
+        // have arrived (loads complete in order).
+        constexpr int YV = 4;  // fragments per lane: 2 nyc1 / (64 NW) with the 8-wave, 32-plane chunks
+        static_assert(NW == 8, "the plane-slot variant takes 8 waves (4 planes per wave and chunk)");
+        Op yv[YV];
         Op xr[2][NZBM][2];
         load_plane(plane_y(0), xr[0]);
         load_plane(plane_y(1), xr[1]);
         for (int s = 0; s < nplanes; s += 2) {  // nplanes is even
+            const int ych = s / per_wave;
+            const bool first = s % per_wave == 0, last = (s + 2) % per_wave == 0;
 #pragma unroll
             for (int zb = 0; zb < NZBM; zb++)
                 if (zb < a.NZB)
 #pragma unroll
                     for (int q = 0; q < 2; q++) ring[(zb * 2 + q) * 64 + lane] = xr[0][zb][q];
+            if (last && ych + 1 < a.NYC) {
+                Op *yb = ybuf + (size_t)((ych + 1) & 1) * 2 * nyc1;
+#pragma unroll
+                for (int k = 0; k < YV; k++) {
+                    const int e = (w * YV + k) * 64 + lane;
+                    if (e < 2 * nyc1) yb[e] = yv[k];
+                }
+            }
+            if (first && ych + 1 < a.NYC) {
+#pragma unroll
+                for (int k = 0; k < YV; k++) {
+                    const int e = (w * YV + k) * 64 + lane;
+                    if (e < 2 * nyc1)
+                        yv[k] = e < nyc1 ? tabY[(size_t)(ych + 1) * nyc1 + e] : tabY_lo[(size_t)(ych + 1) * nyc1 + e - nyc1];
+                }
+            }
             Op x2[NZBM][2];
 #pragma unroll
             for (int zb = 0; zb < NZBM; zb++)
@@ -322,8 +361,9 @@ size_t tzy_lds_bytes(const TzyArgs &a, int elem, bool split, int my, int nbw)
 {
     const size_t zf = (size_t)a.NZB * a.MZ * 64 * 4 * elem * ((split && FNO_TZY_TZ_SPLIT) ? 2 : 1);
     const size_t tl = (size_t)a.Kz * a.Kt * (2 * a.Yc + 4) * elem;
-    if (tzy_ring(elem, a.Kt <= 8 ? 1 : 2, my, nbw))  // the waves' plane slots
-        return (size_t)tzy_ring_offset((int)zf, (int)tl) + (size_t)FNO_TZY_NW_BF16 * a.NZB * 2 * 64 * 4 * elem;
+    if (tzy_ring(elem, a.Kt <= 8 ? 1 : 2, my, nbw))  // the waves' plane slots, two chunks' y basis (hi, lo)
+        return (size_t)tzy_ring_offset((int)zf, (int)tl) +
+               ((size_t)FNO_TZY_NW_BF16 * a.NZB * 2 + (size_t)2 * 2 * (2 * a.Yc / 16) * my) * 64 * 4 * elem;
     return zf + tl;
 }
 
