@@ -51,6 +51,9 @@ SHAPES = {
     # batch 4 at width 32 (the batched CO2 block's): the mix holds the batch in registers and
     # its backward takes 32-mode tiles (64 would not fit in LDS)
     "batch4_w32": (4, 32, 32, (4, 4, 16, 8), (2, 2, 4, 4)),
+    # three chunks of 32 y planes, the last one ragged: the bfloat16 k_tzy_fwd's y basis
+    # double-buffered a chunk ahead and its plane slots over several chunks
+    "tall_y_chunks": (1, 4, 4, (2, 80, 16, 8), (1, 10, 4, 4)),
 }
 
 # the kernels each shape must run on: forward t,z,y (k_tzy_fwd "tzy_fwd", the general
@@ -76,6 +79,7 @@ PATHS = {
     "odd_t45": ("tzy_gen", "zt_block_tsl"),
     "scalar_kt21": ("fwd_tz", "inv_zt_block"),
     "batch4_w32": (PAIR, "zt_block"),
+    "tall_y_chunks": (PAIR, "zt_block"),
 }
 
 
