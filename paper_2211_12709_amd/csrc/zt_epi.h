@@ -67,6 +67,9 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3, ZEPI_ADJ_ACC 
 #ifndef FNO_ZT_GEN_VEC1
 #define FNO_ZT_GEN_VEC1 1  // t-sliced kernels, even Nt: runs of 4 t as one dword-aligned access (else pairs)
 #endif
+#ifndef FNO_ZT_X32
+#define FNO_ZT_X32 1  // bfloat16: paired K chunks as 16x16x32 products in the z and t synthesis
+#endif
 #ifndef FNO_ZT_GELU_BWD
 #define FNO_ZT_GELU_BWD 1  // bfloat16 BWD GELU': 0 A&S 7.1.26, 1 logistic Phi + exact phi, 2 logistic derivative
 #endif
@@ -279,6 +282,9 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
 {
     typedef typename OpOf<T>::type Op;
     constexpr bool PW = EPI != ZEPI_PLAIN;
+    // bfloat16: two K chunks of one accumulator per 16x16x32 product (not in the t-sliced BWD
+    // kernel, where the paired operands cost spills)
+    constexpr bool X32 = sizeof(T) == 2 && FNO_ZT_X32 && !(GEN && EPI == ZEPI_BWD);
     constexpr bool ADJ = EPI == ZEPI_ADJ || EPI == ZEPI_ADJ_ACC;
     const int ZC = a.ZC, LZC = ZC == 8 ? 3 : 4;  // z values per chunk (8 or 16), log2
     extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -673,10 +679,14 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                             const Op ac = kr[i] ? *reinterpret_cast<const Op *>(pcs[i] + qstep * q) : op_zero<T>();
                             const Op as =
                                 kr[i] ? op_sign(*reinterpret_cast<const Op *>(psn[i] + qstep * q), neg[i]) : op_zero<T>();
-                            acc[i] = mma16(ac, zcv, acc[i]);
-                            if (SPLIT && FNO_ZT_P1_SPLIT) acc[i] = mma16(ac, zcl, acc[i]);
-                            acc[i] = mma16(as, zsv, acc[i]);
-                            if (SPLIT && FNO_ZT_P1_SPLIT) acc[i] = mma16(as, zsl, acc[i]);
+                            if (X32 && !FNO_ZT_P1_SPLIT) {
+                                acc[i] = mma32(ac, as, zcv, zsv, acc[i]);
+                            } else {
+                                acc[i] = mma16(ac, zcv, acc[i]);
+                                if (SPLIT && FNO_ZT_P1_SPLIT) acc[i] = mma16(ac, zcl, acc[i]);
+                                acc[i] = mma16(as, zsv, acc[i]);
+                                if (SPLIT && FNO_ZT_P1_SPLIT) acc[i] = mma16(as, zsl, acc[i]);
+                            }
                         }
                     }
 #pragma unroll
@@ -710,10 +720,14 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                             const Op ac = krow ? *reinterpret_cast<const Op *>(p_cos + qstep * q) : op_zero<T>();
                             const Op as = krow ? op_sign(*reinterpret_cast<const Op *>(p_sin + qstep * q), ri == 0)
                                                : op_zero<T>();
-                            acc = mma16(ac, tzc[q], acc);
-                            if (SPLIT && FNO_ZT_P1_SPLIT) acc = mma16(ac, tzcl[q], acc);
-                            acc = mma16(as, tzs[q], acc);
-                            if (SPLIT && FNO_ZT_P1_SPLIT) acc = mma16(as, tzsl[q], acc);
+                            if (X32 && !FNO_ZT_P1_SPLIT) {
+                                acc = mma32(ac, as, tzc[q], tzs[q], acc);
+                            } else {
+                                acc = mma16(ac, tzc[q], acc);
+                                if (SPLIT && FNO_ZT_P1_SPLIT) acc = mma16(ac, tzcl[q], acc);
+                                acc = mma16(as, tzs[q], acc);
+                                if (SPLIT && FNO_ZT_P1_SPLIT) acc = mma16(as, tzsl[q], acc);
+                            }
                         }
                 } else {
                     for (int q = 0; q < QH; q++) {
@@ -763,14 +777,42 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
 #pragma unroll
                 for (int mt = 0; mt < NTQ; mt++) {
                     acc[mt] = f4_zero();
+                    if constexpr (X32) {
+                        // the synthesis and pointwise K chunks of this accumulator, two per product
+                        // (a zero partner for an odd count: one product shape per chain)
+                        constexpr int NP = NTT * (P2S ? 2 : 1) + (PW ? SPAN : 0);
+                        Op pa[NP + 1], pb[NP + 1];
+                        int n = 0;
 #pragma unroll
-                    for (int q = 0; q < NTT; q++) {
-                        acc[mt] = mma16(ta[mt][q], bv[q], acc[mt]);
-                        if (P2S) acc[mt] = mma16(tal[mt][q], bv[q], acc[mt]);
-                    }
-                    if (PW) {
+                        for (int q = 0; q < NTT; q++) {
+                            pa[n] = ta[mt][q];
+                            pb[n++] = bv[q];
+                            if (P2S) {
+                                pa[n] = tal[mt][q];
+                                pb[n++] = bv[q];
+                            }
+                        }
+                        if (PW) {
 #pragma unroll
-                        for (int s = 0; s < SPAN; s++) acc[mt] = mma16(av[s][mt], wd[s], acc[mt]);
+                            for (int s = 0; s < SPAN; s++) {
+                                pa[n] = av[s][mt];
+                                pb[n++] = wd[s];
+                            }
+                        }
+                        pa[NP] = op_zero<T>();
+                        pb[NP] = op_zero<T>();
+#pragma unroll
+                        for (int i = 0; i < NP; i += 2) acc[mt] = mma32(pa[i], pa[i + 1], pb[i], pb[i + 1], acc[mt]);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < NTT; q++) {
+                            acc[mt] = mma16(ta[mt][q], bv[q], acc[mt]);
+                            if (P2S) acc[mt] = mma16(tal[mt][q], bv[q], acc[mt]);
+                        }
+                        if (PW) {
+#pragma unroll
+                            for (int s = 0; s < SPAN; s++) acc[mt] = mma16(av[s][mt], wd[s], acc[mt]);
+                        }
                     }
                 }
                 // epilogue: acc[mt][r] is (t = 4 NTQ g + 4 mt + r, column n)
