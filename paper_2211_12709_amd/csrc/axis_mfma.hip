@@ -22,6 +22,10 @@
 #define FNO_AXIS_BF16_SPLIT 0
 #endif
 
+#ifndef FNO_AXIS_X32
+#define FNO_AXIS_X32 1  // bfloat16 synthesis: two K chunks per 16x16x32 product
+#endif
+
 namespace fno {
 
 struct AxisArgs {
@@ -140,6 +144,7 @@ __global__ void __launch_bounds__(256) k_axis_syn(const float2 *__restrict__ in,
 {
     typedef typename OpOf<TC>::type Op;
     constexpr bool SPLIT = sizeof(TC) == 2 && FNO_AXIS_BF16_SPLIT;
+    constexpr bool X32 = sizeof(TC) == 2 && !SPLIT && FNO_AXIS_X32 && QKM % 2 == 0;
     const int CB = a.CB;
     extern __shared__ __attribute__((aligned(16))) char smem[];
     const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), g = lane >> 4, c = lane & 15;
@@ -183,13 +188,22 @@ __global__ void __launch_bounds__(256) k_axis_syn(const float2 *__restrict__ in,
                 const int mp = mp0 + u;
                 if (mp < half) {
                     f4v accr = f4_zero(), acci = f4_zero();
+                    if constexpr (X32) {
+                        // two K chunks per 16x16x32 product (QKM is even; chunks past QK are zero)
 #pragma unroll
-                    for (int q = 0; q < QKM; q++) {
-                        accr = mma16(ar[u][q], bv[q], accr);
-                        acci = mma16(ai[u][q], bv[q], acci);
-                        if (SPLIT) {
-                            accr = mma16(arl[u][q], bv[q], accr);
-                            acci = mma16(ail[u][q], bv[q], acci);
+                        for (int q = 0; q < QKM; q += 2) {
+                            accr = mma32(ar[u][q], ar[u][q + 1], bv[q], bv[q + 1], accr);
+                            acci = mma32(ai[u][q], ai[u][q + 1], bv[q], bv[q + 1], acci);
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < QKM; q++) {
+                            accr = mma16(ar[u][q], bv[q], accr);
+                            acci = mma16(ai[u][q], bv[q], acci);
+                            if (SPLIT) {
+                                accr = mma16(arl[u][q], bv[q], accr);
+                                acci = mma16(ail[u][q], bv[q], acci);
+                            }
                         }
                     }
 #pragma unroll

@@ -36,6 +36,9 @@ template <typename T> constexpr int tzy_nw() { return sizeof(T) == 2 ? FNO_TZY_N
 #ifndef FNO_TZY_LDS_RING
 #define FNO_TZY_LDS_RING 1  // bfloat16: one plane of each wave's current pair in LDS, the next pair's loads in flight
 #endif
+#ifndef FNO_TZY_Y_X32
+#define FNO_TZY_Y_X32 1  // bfloat16 y step: hi and lo basis products as one 16x16x32 product
+#endif
 #ifndef FNO_TZY_USE
 #define FNO_TZY_USE 1  // dtypes that take this kernel where it applies (bit 0 bfloat16, bit 1 float; else the general one)
 #endif
@@ -260,8 +263,14 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
                                                  : op_zero<T>();
 #pragma unroll
                         for (int mb = 0; mb < MY; mb++) {
-                            acc[nbi][mb] = mma16(ay[mb], bt, acc[nbi][mb]);
-                            if (SPLIT) acc[nbi][mb] = mma16(ayl[mb], bt, acc[nbi][mb]);
+                            // bfloat16: the hi and lo basis products in one 16x16x32 product (all of this
+                            // accumulator's products are)
+                            if (SPLIT && FNO_TZY_Y_X32) {
+                                acc[nbi][mb] = mma32(ay[mb], ayl[mb], bt, bt, acc[nbi][mb]);
+                            } else {
+                                acc[nbi][mb] = mma16(ay[mb], bt, acc[nbi][mb]);
+                                if (SPLIT) acc[nbi][mb] = mma16(ayl[mb], bt, acc[nbi][mb]);
+                            }
                         }
                     }
                 }

@@ -32,6 +32,9 @@
 #define FNO_TZYG_VEC1 1  // bfloat16, even Nt not a multiple of 4: a run of 4 t as one dword-aligned access (else two)
 #endif
 
+#ifndef FNO_TZY_Y_X32
+#define FNO_TZY_Y_X32 1  // bfloat16 y step: hi and lo basis products as one 16x16x32 product
+#endif
 #ifndef FNO_TZY_TZ_SPLIT
 #define FNO_TZY_TZ_SPLIT 0  // bfloat16: hi + lo basis in the t and z steps (0: hi only; their result is staged in bfloat16)
 #endif
@@ -158,8 +161,14 @@ k_tzy_gen(const T *__restrict__ x, float2 *__restrict__ t2, const typename OpOf<
                                              : op_zero<T>();
 #pragma unroll
                     for (int mb = 0; mb < MY; mb++) {
-                        acc[nbi][mb] = mma16(ay[mb], bt, acc[nbi][mb]);
-                        if (SPLIT) acc[nbi][mb] = mma16(ayl[mb], bt, acc[nbi][mb]);
+                        // bfloat16: the hi and lo basis products in one 16x16x32 product (all of this
+                        // accumulator's products are)
+                        if (SPLIT && FNO_TZY_Y_X32) {
+                            acc[nbi][mb] = mma32(ay[mb], ayl[mb], bt, bt, acc[nbi][mb]);
+                        } else {
+                            acc[nbi][mb] = mma16(ay[mb], bt, acc[nbi][mb]);
+                            if (SPLIT) acc[nbi][mb] = mma16(ayl[mb], bt, acc[nbi][mb]);
+                        }
                     }
                 }
             }

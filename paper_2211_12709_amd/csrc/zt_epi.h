@@ -70,6 +70,9 @@ enum { ZEPI_PLAIN = 0, ZEPI_BLOCK = 1, ZEPI_BWD = 2, ZEPI_ADJ = 3, ZEPI_ADJ_ACC 
 #ifndef FNO_ZT_X32
 #define FNO_ZT_X32 1  // bfloat16: paired K chunks as 16x16x32 products in the z and t synthesis
 #endif
+#ifndef FNO_ZT_X32_GW
+#define FNO_ZT_X32_GW 1  // the same for the BWD weight-gradient products (both t tiles per product)
+#endif
 #ifndef FNO_ZT_GELU_BWD
 #define FNO_ZT_GELU_BWD 1  // bfloat16 BWD GELU': 0 A&S 7.1.26, 1 logistic Phi + exact phi, 2 logistic derivative
 #endif
@@ -863,16 +866,23 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                 if (EPI == ZEPI_BWD) {
                     // C[(z', i) = 16 (qlo + s) + 4 g + r][n] += sum_t x[z'][i][t] gz[n][t]; K chunk = t tile mt
                     const int grow = 4 * NTQ * g, gk = gi * ZG * Csp + 16 * qlo + c;
+                    auto gather_x = [&](int mt, int s) {
+                        const int r0 = grow + 4 * mt, k = gk + 16 * s;
+                        const T *xg = xt + (size_t)r0 * ldT;
+                        return op_gather4(xg + xsw(r0, k), xg + ldT + xsw(r0 + 1, k), xg + 2 * ldT + xsw(r0 + 2, k),
+                                          xg + 3 * ldT + xsw(r0 + 3, k));
+                    };
+                    if constexpr (X32 && FNO_ZT_X32_GW && NTQ == 2) {
+                        // both t tiles (K chunks) of each weight-gradient accumulator in one product
+                        const Op bg0 = to_op<T>(acc[0]), bg1 = to_op<T>(acc[1]);
 #pragma unroll
-                    for (int mt = 0; mt < NTQ; mt++) {
-                        const Op bg = to_op<T>(acc[mt]);
+                        for (int s = 0; s < NGW; s++) gwacc[s] = mma32(gather_x(0, s), gather_x(1, s), bg0, bg1, gwacc[s]);
+                    } else {
 #pragma unroll
-                        for (int s = 0; s < NGW; s++) {
-                            const int r0 = grow + 4 * mt, k = gk + 16 * s;
-                            const T *xg = xt + (size_t)r0 * ldT;
-                            const Op ax = op_gather4(xg + xsw(r0, k), xg + ldT + xsw(r0 + 1, k),
-                                                     xg + 2 * ldT + xsw(r0 + 2, k), xg + 3 * ldT + xsw(r0 + 3, k));
-                            gwacc[s] = mma16(ax, bg, gwacc[s]);
+                        for (int mt = 0; mt < NTQ; mt++) {
+                            const Op bg = to_op<T>(acc[mt]);
+#pragma unroll
+                            for (int s = 0; s < NGW; s++) gwacc[s] = mma16(gather_x(mt, s), bg, gwacc[s]);
                         }
                     }
                 }
