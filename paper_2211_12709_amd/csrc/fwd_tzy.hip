@@ -39,6 +39,9 @@ template <typename T> constexpr int tzy_nw() { return sizeof(T) == 2 ? FNO_TZY_N
 #ifndef FNO_TZY_Y_X32
 #define FNO_TZY_Y_X32 1  // bfloat16 y step: hi and lo basis products as one 16x16x32 product
 #endif
+#ifndef FNO_TZY_T_X32
+#define FNO_TZY_T_X32 1  // bfloat16 t step: the two t chunks as one 16x16x32 product
+#endif
 #ifndef FNO_TZY_USE
 #define FNO_TZY_USE 1  // dtypes that take this kernel where it applies (bit 0 bfloat16, bit 1 float; else the general one)
 #endif
@@ -162,17 +165,24 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
 #pragma unroll
                 for (int nt = 0; nt < NTT; nt++) {
                     f4v c0 = f4_zero(), c1 = f4_zero();
+                    if constexpr (SPLIT && !FNO_TZY_TZ_SPLIT && FNO_TZY_T_X32) {
+                        // both t chunks in one 16x16x32 product (a chunk past Nt is zero in the
+                        // fragments and in the basis)
+                        c0 = mma32(fx(0, zb, 0), fx(0, zb, 1), tb[0][nt], tb[1][nt], c0);
+                        c1 = mma32(fx(1, zb, 0), fx(1, zb, 1), tb[0][nt], tb[1][nt], c1);
+                    } else {
 #pragma unroll
-                    for (int q = 0; q < 2; q++)
-                        if (q < a.NQ) {
-                            const Op xa = fx(0, zb, q), xb = fx(1, zb, q);
-                            c0 = mma16(xa, tb[q][nt], c0);
-                            c1 = mma16(xb, tb[q][nt], c1);
-                            if (SPLIT && FNO_TZY_TZ_SPLIT) {
-                                c0 = mma16(xa, tbl[q][nt], c0);
-                                c1 = mma16(xb, tbl[q][nt], c1);
+                        for (int q = 0; q < 2; q++)
+                            if (q < a.NQ) {
+                                const Op xa = fx(0, zb, q), xb = fx(1, zb, q);
+                                c0 = mma16(xa, tb[q][nt], c0);
+                                c1 = mma16(xb, tb[q][nt], c1);
+                                if (SPLIT && FNO_TZY_TZ_SPLIT) {
+                                    c0 = mma16(xa, tbl[q][nt], c0);
+                                    c1 = mma16(xb, tbl[q][nt], c1);
+                                }
                             }
-                        }
+                    }
                     bz[0][nt] = to_op<T>(c0);
                     bz[1][nt] = to_op<T>(c1);
                 }

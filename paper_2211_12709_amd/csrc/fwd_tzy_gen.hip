@@ -32,6 +32,9 @@
 #define FNO_TZYG_VEC1 1  // bfloat16, even Nt not a multiple of 4: a run of 4 t as one dword-aligned access (else two)
 #endif
 
+#ifndef FNO_TZY_T_X32
+#define FNO_TZY_T_X32 1  // bfloat16 t step: t chunks in pairs as 16x16x32 products
+#endif
 #ifndef FNO_TZY_Y_X32
 #define FNO_TZY_Y_X32 1  // bfloat16 y step: hi and lo basis products as one 16x16x32 product
 #endif
@@ -210,13 +213,25 @@ k_tzy_gen(const T *__restrict__ x, float2 *__restrict__ t2, const typename OpOf<
 #pragma unroll
             for (int nt = 0; nt < NTT; nt++) {
                 f4v c1 = f4_zero();
+                if constexpr (SPLIT && !TS && FNO_TZY_T_X32) {
+                    // t chunks in pairs, one 16x16x32 product each (chunks past Nt are zero: the
+                    // fragments by their loads, the basis here)
 #pragma unroll
-                for (int q = 0; q < NQM; q++)
-                    if (q < NQ) {
-                        const int ti = (q * NTT + nt) * 64 + lane;
-                        c1 = mma16(cur[q], tlb[ti], c1);
-                        if (TS) c1 = mma16(cur[q], tlb[ntf + ti], c1);
-                    }
+                    for (int q = 0; q < NQM; q += 2)
+                        if (q < NQ) {
+                            const Op t0 = tlb[(q * NTT + nt) * 64 + lane];
+                            const Op t1 = q + 1 < NQ ? tlb[((q + 1) * NTT + nt) * 64 + lane] : op_zero<T>();
+                            c1 = mma32(cur[q], q + 1 < NQM ? cur[q + 1] : op_zero<T>(), t0, t1, c1);
+                        }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < NQM; q++)
+                        if (q < NQ) {
+                            const int ti = (q * NTT + nt) * 64 + lane;
+                            c1 = mma16(cur[q], tlb[ti], c1);
+                            if (TS) c1 = mma16(cur[q], tlb[ntf + ti], c1);
+                        }
+                }
                 bz[nt] = to_op<T>(c1);
             }
             // z step
