@@ -285,9 +285,10 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
 {
     typedef typename OpOf<T>::type Op;
     constexpr bool PW = EPI != ZEPI_PLAIN;
-    // bfloat16: two K chunks of one accumulator per 16x16x32 product (not in the t-sliced BWD
-    // kernel, where the paired operands cost spills)
-    constexpr bool X32 = sizeof(T) == 2 && FNO_ZT_X32 && !(GEN && EPI == ZEPI_BWD);
+    // bfloat16: two K chunks of one accumulator per 16x16x32 product: in the z synthesis (X32P1)
+    // and in the tiles (X32; not in the t-sliced BWD kernel, where the paired operands cost spills)
+    constexpr bool X32P1 = sizeof(T) == 2 && FNO_ZT_X32;
+    constexpr bool X32 = X32P1 && !(GEN && EPI == ZEPI_BWD);
     constexpr bool ADJ = EPI == ZEPI_ADJ || EPI == ZEPI_ADJ_ACC;
     const int ZC = a.ZC, LZC = ZC == 8 ? 3 : 4;  // z values per chunk (8 or 16), log2
     extern __shared__ __attribute__((aligned(16))) char smem[];
@@ -682,7 +683,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                             const Op ac = kr[i] ? *reinterpret_cast<const Op *>(pcs[i] + qstep * q) : op_zero<T>();
                             const Op as =
                                 kr[i] ? op_sign(*reinterpret_cast<const Op *>(psn[i] + qstep * q), neg[i]) : op_zero<T>();
-                            if (X32 && !FNO_ZT_P1_SPLIT) {
+                            if (X32P1 && !FNO_ZT_P1_SPLIT) {
                                 acc[i] = mma32(ac, as, zcv, zsv, acc[i]);
                             } else {
                                 acc[i] = mma16(ac, zcv, acc[i]);
@@ -723,7 +724,7 @@ __device__ __forceinline__ void zt_epi_body(const typename CplxOf<T>::type *__re
                             const Op ac = krow ? *reinterpret_cast<const Op *>(p_cos + qstep * q) : op_zero<T>();
                             const Op as = krow ? op_sign(*reinterpret_cast<const Op *>(p_sin + qstep * q), ri == 0)
                                                : op_zero<T>();
-                            if (X32 && !FNO_ZT_P1_SPLIT) {
+                            if (X32P1 && !FNO_ZT_P1_SPLIT) {
                                 acc = mma32(ac, as, tzc[q], tzs[q], acc);
                             } else {
                                 acc = mma16(ac, tzc[q], acc);
