@@ -42,6 +42,9 @@ template <typename T> constexpr int tzy_nw() { return sizeof(T) == 2 ? FNO_TZY_N
 #ifndef FNO_TZY_T_X32
 #define FNO_TZY_T_X32 1  // bfloat16 t step: the two t chunks as one 16x16x32 product
 #endif
+#ifndef FNO_TZY_YPAIR
+#define FNO_TZY_YPAIR 1  // a wave's plane pair adjacent in y: its T1 values staged as pairs
+#endif
 #ifndef FNO_TZY_USE
 #define FNO_TZY_USE 1  // dtypes that take this kernel where it applies (bit 0 bfloat16, bit 1 float; else the general one)
 #endif
@@ -54,6 +57,10 @@ template <typename T> constexpr int tzy_nw() { return sizeof(T) == 2 ? FNO_TZY_N
 
 namespace fno {
 
+
+// Two values as one 4-byte (bfloat16) or 8-byte (float) store at p (2-element aligned).
+__device__ __forceinline__ void st_pair_t(float *p, float a, float b) { *reinterpret_cast<float2 *>(p) = make_float2(a, b); }
+__device__ __forceinline__ void st_pair_t(__bf16 *p, float a, float b) { *reinterpret_cast<unsigned *>(p) = bf16_pack2(a, b); }
 
 // Byte offset of the plane slots in LDS: after the z-basis fragments and the T1 chunk (16-aligned).
 __host__ __device__ constexpr int tzy_ring_offset(int zbytes, int tbytes) { return (zbytes + tbytes + 15) / 16 * 16; }
@@ -143,7 +150,11 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
     __syncthreads();
 
     const int nplanes = a.NYC * per_wave;  // plane slots of this wave
-    auto plane_y = [&](int s) { return (s / per_wave) * a.Yc + (s % per_wave) * NW + w; };
+    // YP: a wave's planes of a chunk are consecutive in y (yl = per_wave w + slot), so that a pair's
+    // T1 values are neighbours; else interleaved over the waves (yl = NW slot + w)
+    constexpr bool YP = FNO_TZY_YPAIR;
+    auto plane_yl = [&](int s) { return YP ? w * per_wave + s % per_wave : (s % per_wave) * NW + w; };
+    auto plane_y = [&](int s) { return (s / per_wave) * a.Yc + plane_yl(s); };
     // t and z steps of two planes (s, s + 1) at once: every z-basis fragment read
     // from LDS feeds both planes, and the two independent MFMA chains overlap.
     // Planes beyond Ny have zero input (guarded loads), hence a zero spectrum.
@@ -210,34 +221,58 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
                     }
             }
         }
-        // combine cos/sin halves into the complex spectrum and stage it in LDS
+        // combine cos/sin halves into the complex spectrum and stage it in LDS; with YP the two
+        // planes are neighbours in y and their values go out as one pair
+        auto combine = [&](int u, int kb, int nt, f4v &v) {
+            if (NTT == 1) {
 #pragma unroll
-        for (int u = 0; u < 2; u++) {
-            const int yl = ((s + u) % per_wave) * NW + w;
+                for (int r = 0; r < 4; r++) {
+                    const float ps = row_ror8(Ps[u][kb][0][r]);
+                    v[r] = c < 8 ? Pc[u][kb][0][r] + ps : Pc[u][kb][0][r] - ps;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+                    v[r] = nt == 0 ? Pc[u][kb][0][r] + Ps[u][kb][NTT - 1][r] : Pc[u][kb][NTT - 1][r] - Ps[u][kb][0][r];
+            }
+        };
+        const int ri_l = NTT == 1 ? (c >> 3) : 0, kt = NTT == 1 ? (c & 7) : c;
+        if constexpr (YP) {
+            const int yl = plane_yl(s);  // even: the pair (yl, yl + 1)
 #pragma unroll
             for (int kb = 0; kb < MAXKB; kb++) {
                 if (kb < a.KB) {
 #pragma unroll
                     for (int nt = 0; nt < NTT; nt++) {
-                        f4v v;
-                        if (NTT == 1) {
-#pragma unroll
-                            for (int r = 0; r < 4; r++) {
-                                const float ps = row_ror8(Ps[u][kb][0][r]);
-                                v[r] = c < 8 ? Pc[u][kb][0][r] + ps : Pc[u][kb][0][r] - ps;
-                            }
-                        } else {
-#pragma unroll
-                            for (int r = 0; r < 4; r++)
-                                v[r] = nt == 0 ? Pc[u][kb][0][r] + Ps[u][kb][NTT - 1][r]
-                                               : Pc[u][kb][NTT - 1][r] - Ps[u][kb][0][r];
-                        }
-                        const int ri = NTT == 1 ? (c >> 3) : nt;
-                        const int kt = NTT == 1 ? (c & 7) : c;
+                        f4v v0, v1;
+                        combine(0, kb, nt, v0);
+                        combine(1, kb, nt, v1);
+                        const int ri = NTT == 1 ? ri_l : nt;
 #pragma unroll
                         for (int r = 0; r < 4; r++) {
                             const int kz = kb * 16 + 4 * g + r;
-                            if (kz < Kz && kt < Kt) tl[(kz * Kt + kt) * ldk + ri * a.Yc + yl] = from_f32<T>(v[r]);
+                            if (kz < Kz && kt < Kt) st_pair_t(tl + (kz * Kt + kt) * ldk + ri * a.Yc + yl, v0[r], v1[r]);
+                        }
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 2; u++) {
+                const int yl = plane_yl(s + u);
+#pragma unroll
+                for (int kb = 0; kb < MAXKB; kb++) {
+                    if (kb < a.KB) {
+#pragma unroll
+                        for (int nt = 0; nt < NTT; nt++) {
+                            f4v v;
+                            combine(u, kb, nt, v);
+                            const int ri = NTT == 1 ? ri_l : nt;
+#pragma unroll
+                            for (int r = 0; r < 4; r++) {
+                                const int kz = kb * 16 + 4 * g + r;
+                                if (kz < Kz && kt < Kt) tl[(kz * Kt + kt) * ldk + ri * a.Yc + yl] = from_f32<T>(v[r]);
+                            }
                         }
                     }
                 }
