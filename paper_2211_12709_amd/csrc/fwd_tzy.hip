@@ -92,7 +92,8 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
 
     // LDS: z-basis fragments (hi [+ lo where the z step uses it]) then the T1 chunk [col][k] with
     // row stride ldk.
-    // RING: then each wave's slot for the first plane of its current pair, [z block][t chunk][lane].
+    // RING: then each wave's slot for the first plane of its current pair, [z block][lane][t chunk]
+    // (a lane's two fragments side by side: one 16-byte access).
     constexpr bool TS = SPLIT && FNO_TZY_TZ_SPLIT;
     constexpr bool RING = tzy_ring(sizeof(T), NTT, MY, NBW);
     const int nzf = a.NZB * a.MZ * 64;
@@ -344,7 +345,7 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
             for (int zb = 0; zb < NZBM; zb++)
                 if (zb < a.NZB)
 #pragma unroll
-                    for (int q = 0; q < 2; q++) ring[(zb * 2 + q) * 64 + lane] = xr[0][zb][q];
+                    for (int q = 0; q < 2; q++) ring[(zb * 64 + lane) * 2 + q] = xr[0][zb][q];
             if (last && ych + 1 < a.NYC) {
                 Op *yb = ybuf + (size_t)((ych + 1) & 1) * 2 * nyc1;
 #pragma unroll
@@ -370,7 +371,7 @@ __global__ void __launch_bounds__(64 * tzy_nw<T>()) __attribute__((amdgpu_waves_
                 load_plane(plane_y(s + 2), xr[0]);
                 load_plane(plane_y(s + 3), xr[1]);
             }
-            do_pair(s, [&](int u, int zb, int q) { return u == 0 ? ring[(zb * 2 + q) * 64 + lane] : x2[zb][q]; });
+            do_pair(s, [&](int u, int zb, int q) { return u == 0 ? ring[(zb * 64 + lane) * 2 + q] : x2[zb][q]; });
             chunk_end(s + 1);
         }
     } else {
