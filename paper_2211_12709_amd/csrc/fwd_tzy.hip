@@ -52,7 +52,7 @@ template <typename T> constexpr int tzy_nw() { return sizeof(T) == 2 ? FNO_TZY_N
 #define FNO_TZY_TZ_SPLIT 0  // bfloat16: hi + lo basis in the t and z steps (0: hi only; their result is staged in bfloat16)
 #endif
 #ifndef FNO_TZY_WAVES_F32
-#define FNO_TZY_WAVES_F32 1  // the same for the float kernel
+#define FNO_TZY_WAVES_F32 1  // waves per SIMD the float kernel is compiled for
 #endif
 
 namespace fno {
